@@ -1,0 +1,75 @@
+"""Seeded input generators and the HNSW base-graph builder (inputs to both
+the oracle and the GPU path): determinism, shapes, value ranges, and the
+structural invariants of an HNSW graph (Sec. 2.2 of the U-HNSW paper: a
+layered proximity graph with at most M neighbours per node on upper layers
+and 2M on layer 0)."""
+import numpy as np
+import pytest
+
+import synth
+import synth.graphs as sg
+
+
+def test_workload_determinism_and_shapes():
+    a = synth.make_workload(1)
+    b = synth.make_workload(1)
+    assert a.digest() == b.digest()
+    assert a.base.shape == (10_000, 32) and a.queries.shape == (100, 32)
+    assert a.base.dtype == np.float32 and (a.k == 10).all() and (a.ef == 64).all()
+    assert ((a.p > 0.5) | (a.p == 0.5)).all() and (a.p <= 2.0).all()
+
+
+def test_mixture_integer_range():
+    w = synth.make_workload(2, n=5000, nq=64)
+    assert w.base.shape == (5000, 128)
+    assert (w.base == np.rint(w.base)).all() and w.base.min() >= 0 and w.base.max() <= 255
+    np.testing.assert_array_equal(w.p[:16], synth.P_GRID)
+    np.testing.assert_array_equal(w.p[16:32], synth.P_GRID)
+
+
+def test_other_workloads_small():
+    w3 = synth.make_workload(3, n=200, nq=5)
+    assert (w3.base >= 0).all() and w3.d == 960
+    w4 = synth.make_workload(4, n=300, nq=30)
+    np.testing.assert_allclose(np.linalg.norm(w4.base, axis=1), 1.0, rtol=1e-5)
+    assert list(w4.k[:6]) == [1, 10, 100, 1, 10, 100]
+    assert (w4.ef >= w4.k).all() and (w4.ef <= 512).all()
+    w5 = synth.make_workload(5, n=300, nq=50)
+    assert set(np.unique(w5.k)) <= {10, 100} and w5.d == 96
+
+
+@pytest.mark.parametrize("metric", [1, 2])
+def test_graph_invariants(wl1, metric):
+    wl, g1, g2 = wl1
+    g = g1 if metric == 1 else g2
+    n, M = g.n, g.M
+    assert g.levels[g.entry] == g.max_level == g.levels.max()
+    for l, L in enumerate(g.layers):
+        nodes = np.arange(n) if l == 0 else L.nodes
+        np.testing.assert_array_equal(nodes, np.nonzero(g.levels >= l)[0])
+        deg = np.diff(L.row_ptr)
+        assert deg.max() <= (2 * M if l == 0 else M)
+        on_layer = np.zeros(n, bool)
+        on_layer[nodes] = True
+        assert on_layer[L.col].all()  # neighbours live on the same layer
+        for r in range(0, len(nodes), max(1, len(nodes) // 200)):
+            row = L.col[L.row_ptr[r]:L.row_ptr[r + 1]]
+            assert nodes[r] not in row and len(set(row.tolist())) == len(row)
+    assert np.diff(g.layers[0].row_ptr).min() >= 1
+
+
+def test_level_law(wl1):
+    wl, g1, _ = wl1
+    frac = (g1.levels >= 1).mean()
+    assert abs(frac - 1 / g1.M) < 0.02  # P(level >= 1) = exp(-1/mL) = 1/M
+
+
+def test_builder_thread_independent():
+    rng = np.random.Generator(np.random.PCG64(12))
+    base = rng.standard_normal((3000, 16)).astype(np.float32)
+    a = sg.build_graph(base, 2, M=8, ef_construction=40, seed=5, threads=1, cache=False)
+    b = sg.build_graph(base, 2, M=8, ef_construction=40, seed=5, threads=7, cache=False)
+    assert a.entry == b.entry and a.max_level == b.max_level
+    for la, lb in zip(a.layers, b.layers):
+        np.testing.assert_array_equal(la.row_ptr, lb.row_ptr)
+        np.testing.assert_array_equal(la.col, lb.col)
