@@ -1,0 +1,179 @@
+/*
+ * libuhnsw -- the U-HNSW query path on one AMD Instinct MI355X (gfx950).
+ *
+ * Problem (U-HNSW paper, Wang, Meng, Xu, EDBT'27; Sec. 1.1 and Sec. 2.1):
+ * each query is a tuple (q, p) with its own K; the answer is the top-K of
+ * the dataset under the L_p distance d_p(x, q) = (sum_i |x_i - q_i|^p)^(1/p),
+ * p in [0.5, 2]. Method (Sec. 3.1, Algorithm 1): pick G1 (an HNSW graph
+ * built under L1) when p <= 1.4, else G2 (under L2); run HNSW's KnnSearch on
+ * it to get t candidates C ordered by the base metric; verify C in batches
+ * of kappa under L_p and stop once |R_new n R| / K >= tau.
+ *
+ * Conventions for every entry point:
+ *   - plain C; no exception crosses the boundary;
+ *   - return 0 (UHNSW_OK) or a negative UHNSW_E* code; on error nothing is
+ *     written to any output and uhnsw_last_error(ctx) describes the failure;
+ *   - the caller owns every array it passes; the library copies what it
+ *     keeps (the index) and owns all device memory it allocates;
+ *   - one context may be used by one host thread at a time.
+ */
+#ifndef UHNSW_H
+#define UHNSW_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UHNSW_OK 0
+#define UHNSW_EINVAL (-1)      /* bad argument (NULL, size, range)            */
+#define UHNSW_ENOMEM (-2)      /* host or device allocation failed            */
+#define UHNSW_EDEVICE (-3)     /* a HIP call failed; context is now failed    */
+#define UHNSW_ESTATE (-4)      /* search before load, or failed context       */
+#define UHNSW_EIO (-5)         /* reserved for file loaders                   */
+#define UHNSW_EBUSY (-6)       /* admission budget exhausted (serving)        */
+#define UHNSW_EUNSUPPORTED (-7)/* shape the kernels were not built for        */
+
+#define UHNSW_MAX_LAYERS 32
+#define UHNSW_KMAX 256         /* largest K per query                          */
+#define UHNSW_EFMAX 1024       /* largest efSearch per query                   */
+#define UHNSW_DMAX 1024        /* largest dimension                            */
+
+/* Storage of the base vectors read by the candidate walk. Verification
+ * always reads FP32 copies. */
+#define UHNSW_STORE_F32 0
+#define UHNSW_STORE_BF16 1     /* bfloat16, rounded to nearest even            */
+#define UHNSW_STORE_F16 2      /* IEEE binary16, rounded to nearest even       */
+
+/* per-query flag bits in uhnsw_stats.flags */
+#define UHNSW_QBAD 1           /* query invalid (parameters, non-finite q):
+                                  the row is left padded                      */
+#define UHNSW_QCAP 2           /* walk stopped after n expansions (cannot
+                                  happen for finite inputs; a safety bound)   */
+
+typedef struct uhnsw_ctx uhnsw_ctx;
+
+/* One HNSW graph as per-layer CSR (HNSW's layered proximity graph, Sec. 2.2).
+ * Layer 0 holds every node 0..n-1: row_ptr[0] has n+1 entries. Layer l >= 1
+ * holds the nodes with level >= l, listed ascending in nodes[l] (n_nodes[l]
+ * of them); row_ptr[l] has n_nodes[l]+1 entries indexing col[l]. Degrees are
+ * at most 2M on layer 0 and M above; neighbours of a layer-l node are on
+ * layer l; entry_point has level max_level. All host pointers. */
+typedef struct {
+    int32_t M;
+    int32_t max_level;
+    int32_t entry_point;
+    const int8_t *level;                          /* [n]                       */
+    int64_t n_nodes[UHNSW_MAX_LAYERS];
+    const int32_t *nodes[UHNSW_MAX_LAYERS];       /* layer >= 1                */
+    const int64_t *row_ptr[UHNSW_MAX_LAYERS];
+    const int32_t *col[UHNSW_MAX_LAYERS];
+} uhnsw_graph;
+
+/* The resident index: base vectors (host, n x d FP32 row-major) and the two
+ * base graphs, graphs[0] = G1 (built under L1), graphs[1] = G2 (under L2). */
+typedef struct {
+    int64_t n;
+    int32_t d;
+    const float *base;
+    int32_t storage;          /* UHNSW_STORE_* for the walk                   */
+    uhnsw_graph graphs[2];
+} uhnsw_index;
+
+/* Algorithm 1's parameters (Sec. 3.1) and execution knobs. */
+typedef struct {
+    double tau;               /* early-termination threshold, default 0.92    */
+    float cutoff;             /* G1 when p <= cutoff (FP32 compare), 1.4      */
+    int32_t t;                /* candidates; 0 -> min(ef, 6K), else min(ef,t) */
+    int32_t kappa;            /* batch size; 0 -> max(K, 2)                   */
+    int32_t beam_width;       /* nodes expanded per walk step, 1 = HNSW       */
+    int32_t early_abort;      /* exact partial-sum abort in verification      */
+    int32_t visited_slots;    /* LDS visited-cache slots; 0 -> automatic      */
+    int32_t waves_per_block;  /* 0 -> automatic                               */
+    int32_t persistent;       /* 1: one persistent launch with work stealing  */
+    int32_t timing;           /* 1: record per-kernel times (uhnsw_last_timing)*/
+} uhnsw_params;
+
+/* Per-query counters (the N_b / N_p of the paper's cost model, Eq. 1). */
+typedef struct {
+    int32_t graph;            /* 1 = G1, 2 = G2                               */
+    int32_t n_b;              /* base-metric distances (descent + layer 0)    */
+    int32_t n_exp;            /* layer-0 expansions                           */
+    int32_t n_p;              /* L_p distances evaluated                      */
+    int32_t batches;          /* verification batches taken                   */
+    int32_t nc;               /* |C|                                          */
+    int32_t flags;            /* UHNSW_QBAD, ...                              */
+    int32_t entry0;           /* layer-0 start node (end of the descent)      */
+    uint32_t t_begin;         /* device wall clock when the walk of this query
+                                 started / when its verification ended: low
+                                 32 bits of a counter running at
+                                 hipDeviceAttributeWallClockRate kHz           */
+    uint32_t t_end;
+} uhnsw_stats;
+
+/* Fill *prm with the defaults above. */
+void uhnsw_default_params(uhnsw_params *prm);
+
+/* Create a context on HIP device `device`. *out receives the handle.
+ * Errors: EINVAL (out NULL, no such device), EDEVICE, ENOMEM. */
+int uhnsw_create(int device, uhnsw_ctx **out);
+
+/* Free the context and all device memory it owns. NULL is a no-op. */
+void uhnsw_destroy(uhnsw_ctx *ctx);
+
+/* Message for the last failure on ctx (or of uhnsw_create when ctx is NULL).
+ * The string is owned by the library and valid until the next call on ctx. */
+const char *uhnsw_last_error(const uhnsw_ctx *ctx);
+
+/* Validate the index and copy it to the device, replacing any loaded index.
+ * Layer 0 becomes fixed-degree rows of 2M ids (-1 padded); upper layers get
+ * M-wide rows addressed through a per-node offset; base vectors get a padded
+ * row pitch (zeros) and, for BF16/F16 storage, a converted walk copy.
+ * Errors: EINVAL (any structural violation: id out of range, degree above
+ * 2M / M, neighbour not on the layer, entry point not on the top layer,
+ * d > UHNSW_DMAX, M0 > 64, a non-finite base value), ENOMEM, EDEVICE. */
+int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
+
+/* Search nq queries (host arrays, synchronous).
+ *   queries [nq x d] FP32; p [nq]; k [nq]; ef [nq]; prm may be NULL.
+ *   ids [nq x k_stride] int64 and dists [nq x k_stride] FP32 receive, per
+ *   row, min(k[i], |C_i|) results ascending by (L_p distance, id); the rest
+ *   of the row is id -1, dist +inf. stats [nq] may be NULL.
+ * Errors: EINVAL (NULL pointer, nq < 0, p not finite or outside [0.5, 2],
+ * k < 1 or > UHNSW_KMAX, ef < k or > UHNSW_EFMAX, k_stride < max k, a
+ * non-finite query value),
+ * ESTATE (no index), ENOMEM, EDEVICE. */
+int uhnsw_search(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                 const int32_t *ef, const uhnsw_params *prm, int32_t k_stride, int64_t *ids, float *dists,
+                 uhnsw_stats *stats);
+
+/* Same search on device pointers, asynchronous on `stream` (a hipStream_t;
+ * NULL = the null stream). The caller promises k[i] <= k_max and
+ * ef[i] <= ef_max (host scalars sizing LDS); a query whose values break
+ * this or the ranges above, or whose vector is not finite, is not searched:
+ * its row is padded and its stats get UHNSW_QBAD. cand_ids / cand_keys (device, [nq x c_stride], may be
+ * NULL) receive C and its base-metric keys (-1 / +inf padded). Buffers are
+ * borrowed until the stream's work completes.
+ * Errors: EINVAL (host-checkable arguments), ESTATE, ENOMEM, EDEVICE. */
+int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm,
+                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                        float *cand_keys, int32_t c_stride, void *stream);
+
+/* Lane layout of the walk's FP32 base distance for the loaded index:
+ * element j is summed by lane (j / v) mod g, lanes combine pairwise. */
+int uhnsw_get_layout(const uhnsw_ctx *ctx, int32_t *g, int32_t *v);
+
+/* Device facts for callers that interpret uhnsw_stats: compute units and the
+ * rate (kHz) of the wall clock behind t_begin / t_end. */
+int uhnsw_device_info(const uhnsw_ctx *ctx, int32_t *num_cus, int32_t *wall_clock_khz);
+
+/* Kernel times (ms) of the last search run with prm->timing = 1, measured
+ * with HIP events on the stream the kernels ran on. */
+int uhnsw_last_timing(const uhnsw_ctx *ctx, float *walk_ms, float *verify_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UHNSW_H */

@@ -1,0 +1,543 @@
+// Host side of libuhnsw: context, validation, upload of the index to the
+// device layout, and launch planning for the walk and verify kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "uhnsw.h"
+#include "uhnsw_internal.h"
+
+using namespace uhnsw;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t ensure(size_t want) {
+        if (want <= bytes && p) return hipSuccess;
+        reset();
+        hipError_t e = hipMalloc(&p, want ? want : 1);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    template <typename T>
+    T *as() const {
+        return reinterpret_cast<T *>(p);
+    }
+};
+
+struct GraphDev {
+    DevBuf adj0, up_off, up_adj;
+    int32_t entry = 0, max_level = 0, M = 0, M0 = 0;
+};
+
+}  // namespace
+
+struct uhnsw_ctx {
+    int device = 0;
+    int num_cus = 0;
+    hipStream_t stream = nullptr;
+    bool loaded = false;
+    bool failed = false;
+    std::string err;
+    // index
+    int64_t n = 0;
+    int32_t d = 0, storage = 0, layout = 0;
+    int64_t pitch = 0;
+    DevBuf f32_base, walk_base;
+    GraphDev g[2];
+    // per-search scratch
+    DevBuf cand_ids, cand_keys, ncand, stats, counter, mtab;
+    double mtab_tau = -1.0;
+    // staging for the host-pointer entry point
+    DevBuf s_q, s_p, s_k, s_ef, s_ids, s_dists, s_stats;
+    // timing
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
+};
+
+namespace {
+
+int fail(uhnsw_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+    return code;
+}
+
+int dev_fail(uhnsw_ctx *c, hipError_t e, const char *what) {
+    c->failed = true;
+    return fail(c, e == hipErrorOutOfMemory ? UHNSW_ENOMEM : UHNSW_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(ctx, call)                             \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return dev_fail(ctx, e_, #call); \
+    } while (0)
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Validate one graph against n and the node levels; returns 0 or EINVAL.
+int check_graph(uhnsw_ctx *c, const uhnsw_graph &g, int64_t n, int which) {
+    const char *nm = which == 0 ? "G1" : "G2";
+    if (g.M < 1 || 2 * g.M > kWave) return fail(c, UHNSW_EINVAL, "%s: M=%d outside [1, 32]", nm, g.M);
+    if (g.max_level < 0 || g.max_level >= UHNSW_MAX_LAYERS)
+        return fail(c, UHNSW_EINVAL, "%s: max_level=%d outside [0, %d)", nm, g.max_level, UHNSW_MAX_LAYERS);
+    if (!g.level || !g.row_ptr[0] || (!g.col[0] && n > 0))
+        return fail(c, UHNSW_EINVAL, "%s: NULL level/row_ptr/col", nm);
+    if (g.entry_point < 0 || g.entry_point >= n) return fail(c, UHNSW_EINVAL, "%s: entry point out of range", nm);
+    int top = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (g.level[v] < 0 || g.level[v] >= UHNSW_MAX_LAYERS)
+            return fail(c, UHNSW_EINVAL, "%s: level[%lld] out of range", nm, (long long)v);
+        top = std::max<int>(top, g.level[v]);
+    }
+    if (top != g.max_level || g.level[g.entry_point] != g.max_level)
+        return fail(c, UHNSW_EINVAL, "%s: entry point is not on the top layer %d", nm, g.max_level);
+    for (int l = 0; l <= g.max_level; ++l) {
+        const int64_t *rp = g.row_ptr[l];
+        const int32_t *col = g.col[l];
+        const int64_t rows = l == 0 ? n : g.n_nodes[l];
+        const int deg_max = l == 0 ? 2 * g.M : g.M;
+        if (!rp || (l > 0 && !g.nodes[l])) return fail(c, UHNSW_EINVAL, "%s: layer %d arrays missing", nm, l);
+        int64_t on_layer = 0;
+        for (int64_t v = 0; v < n; ++v) on_layer += g.level[v] >= l;
+        if (rows != on_layer)
+            return fail(c, UHNSW_EINVAL, "%s: layer %d lists %lld nodes, levels say %lld", nm, l, (long long)rows,
+                        (long long)on_layer);
+        if (rp[0] != 0) return fail(c, UHNSW_EINVAL, "%s: layer %d row_ptr[0] != 0", nm, l);
+        for (int64_t r = 0; r < rows; ++r) {
+            if (l > 0) {
+                const int32_t v = g.nodes[l][r];
+                if (v < 0 || v >= n || g.level[v] < l || (r > 0 && g.nodes[l][r - 1] >= v))
+                    return fail(c, UHNSW_EINVAL, "%s: layer %d nodes not ascending ids on the layer", nm, l);
+            }
+            const int64_t deg = rp[r + 1] - rp[r];
+            if (deg < 0 || deg > deg_max)
+                return fail(c, UHNSW_EINVAL, "%s: layer %d row %lld degree %lld outside [0, %d]", nm, l,
+                            (long long)r, (long long)deg, deg_max);
+            for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+                const int32_t u = col[e];
+                if (u < 0 || u >= n || g.level[u] < l)
+                    return fail(c, UHNSW_EINVAL, "%s: layer %d edge to %d not on the layer", nm, l, u);
+            }
+        }
+    }
+    return UHNSW_OK;
+}
+
+int upload_graph(uhnsw_ctx *c, const uhnsw_graph &g, int64_t n, GraphDev &gd) {
+    const int M = g.M, M0 = 2 * g.M;
+    std::vector<int32_t> adj0((size_t)n * M0, -1);
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t b = g.row_ptr[0][v], e = g.row_ptr[0][v + 1];
+        for (int64_t i = b; i < e; ++i) adj0[(size_t)v * M0 + (i - b)] = g.col[0][i];
+    }
+    std::vector<int32_t> up_off((size_t)n, -1);
+    int64_t rows = 0;
+    for (int64_t v = 0; v < n; ++v)
+        if (g.level[v] > 0) {
+            up_off[v] = (int32_t)rows;
+            rows += g.level[v];
+        }
+    if (rows >= (int64_t)INT32_MAX / std::max(M, 1)) return fail(c, UHNSW_EINVAL, "upper layers too large");
+    std::vector<int32_t> up_adj((size_t)std::max<int64_t>(rows, 1) * M, -1);
+    for (int l = 1; l <= g.max_level; ++l) {
+        for (int64_t r = 0; r < g.n_nodes[l]; ++r) {
+            const int32_t v = g.nodes[l][r];
+            const int64_t row = up_off[v] + (l - 1);
+            const int64_t b = g.row_ptr[l][r], e = g.row_ptr[l][r + 1];
+            for (int64_t i = b; i < e; ++i) up_adj[(size_t)row * M + (i - b)] = g.col[l][i];
+        }
+    }
+    HIP_OR_FAIL(c, gd.adj0.ensure(adj0.size() * 4));
+    HIP_OR_FAIL(c, gd.up_off.ensure(up_off.size() * 4));
+    HIP_OR_FAIL(c, gd.up_adj.ensure(up_adj.size() * 4));
+    HIP_OR_FAIL(c, hipMemcpy(gd.adj0.p, adj0.data(), adj0.size() * 4, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(c, hipMemcpy(gd.up_off.p, up_off.data(), up_off.size() * 4, hipMemcpyHostToDevice));
+    HIP_OR_FAIL(c, hipMemcpy(gd.up_adj.p, up_adj.data(), up_adj.size() * 4, hipMemcpyHostToDevice));
+    gd.entry = g.entry_point;
+    gd.max_level = g.max_level;
+    gd.M = M;
+    gd.M0 = M0;
+    return UHNSW_OK;
+}
+
+struct Plan {
+    int ef_cap, vis_bits, kv_cap, wpb, walk_bytes, verify_bytes;
+};
+
+int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan *pl) {
+    pl->ef_cap = round_up(std::max(ef_max, 1), 4);
+    int slots = prm.visited_slots;
+    if (slots <= 0) slots = ef_max <= 64 ? 2048 : ef_max <= 256 ? 4096 : 8192;
+    int bits = 0;
+    while ((1 << bits) < slots) ++bits;
+    if (bits < 6 || bits > 14) return fail(c, UHNSW_EINVAL, "visited_slots %d outside [64, 16384]", slots);
+    pl->vis_bits = bits;
+    const int kappa_max = prm.kappa > 0 ? prm.kappa : std::max(k_max, 2);
+    pl->kv_cap = round_up(std::max(k_max, kappa_max), 4);
+    pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits);
+    pl->verify_bytes = verify_lds_bytes(pl->kv_cap);
+    const int per_wave = std::max(pl->walk_bytes, pl->verify_bytes);
+    pl->wpb = prm.waves_per_block > 0 ? prm.waves_per_block : std::max(1, std::min(4, 65536 / per_wave));
+    if (pl->wpb > 4) return fail(c, UHNSW_EINVAL, "waves_per_block %d > 4", pl->wpb);
+    if ((size_t)pl->walk_bytes * pl->wpb > 64 * 1024 || (size_t)pl->verify_bytes * pl->wpb > 64 * 1024)
+        return fail(c, UHNSW_EUNSUPPORTED, "LDS plan %d B/wave x %d waves exceeds 64 KiB per block",
+                    std::max(pl->walk_bytes, pl->verify_bytes), pl->wpb);
+    return UHNSW_OK;
+}
+
+int ensure_mtab(uhnsw_ctx *c, double tau) {
+    if (c->mtab.p && c->mtab_tau == tau) return UHNSW_OK;
+    int32_t tab[UHNSW_KMAX + 1];
+    tab[0] = 0;
+    for (int K = 1; K <= UHNSW_KMAX; ++K) tab[K] = (int32_t)std::ceil(tau * (double)K - 1e-9);
+    HIP_OR_FAIL(c, c->mtab.ensure(sizeof tab));
+    HIP_OR_FAIL(c, hipMemcpy(c->mtab.p, tab, sizeof tab, hipMemcpyHostToDevice));
+    c->mtab_tau = tau;
+    return UHNSW_OK;
+}
+
+int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
+    if (!(prm.tau > 0.0) || !std::isfinite(prm.tau)) return fail(c, UHNSW_EINVAL, "tau must be positive");
+    if (!std::isfinite(prm.cutoff)) return fail(c, UHNSW_EINVAL, "cutoff must be finite");
+    if (prm.t < 0 || prm.kappa < 0) return fail(c, UHNSW_EINVAL, "t and kappa must be >= 0");
+    if (prm.beam_width < 1 || prm.beam_width > 2) return fail(c, UHNSW_EINVAL, "beam_width must be 1 or 2");
+    for (int i = 0; i < 2; ++i)
+        if (prm.beam_width * c->g[i].M0 > kUCap)
+            return fail(c, UHNSW_EINVAL, "beam_width %d x 2M = %d exceeds %d lanes", prm.beam_width,
+                        prm.beam_width * c->g[i].M0, kUCap);
+    return UHNSW_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+void uhnsw_default_params(uhnsw_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->tau = 0.92;
+    p->cutoff = 1.4f;
+    p->beam_width = 1;
+    p->early_abort = 1;
+}
+
+int uhnsw_create(int device, uhnsw_ctx **out) {
+    if (!out) {
+        g_create_error = "out is NULL";
+        return UHNSW_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || device < 0 || device >= ndev) {
+        g_create_error = "no HIP device " + std::to_string(device) + " (" +
+                         (e != hipSuccess ? hipGetErrorString(e) : std::to_string(ndev) + " present") + ")";
+        return e != hipSuccess ? UHNSW_EDEVICE : UHNSW_EINVAL;
+    }
+    uhnsw_ctx *c = new (std::nothrow) uhnsw_ctx();
+    if (!c) {
+        g_create_error = "out of host memory";
+        return UHNSW_ENOMEM;
+    }
+    c->device = device;
+    if ((e = hipSetDevice(device)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+        g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+        delete c;
+        return UHNSW_EDEVICE;
+    }
+    for (auto &ev : c->ev)
+        if ((e = hipEventCreate(&ev)) != hipSuccess) {
+            g_create_error = std::string("hipEventCreate: ") + hipGetErrorString(e);
+            uhnsw_destroy(c);
+            return UHNSW_EDEVICE;
+        }
+    *out = c;
+    return UHNSW_OK;
+}
+
+void uhnsw_destroy(uhnsw_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    DevBuf *bufs[] = {&c->f32_base, &c->walk_base, &c->cand_ids, &c->cand_keys, &c->ncand, &c->stats,
+                      &c->counter, &c->mtab, &c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids, &c->s_dists,
+                      &c->s_stats};
+    for (DevBuf *b : bufs) b->reset();
+    for (auto &g : c->g) {
+        g.adj0.reset();
+        g.up_off.reset();
+        g.up_adj.reset();
+    }
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *uhnsw_last_error(const uhnsw_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
+    if (!c) return UHNSW_EINVAL;
+    if (!idx || !idx->base) return fail(c, UHNSW_EINVAL, "index or base is NULL");
+    if (idx->n < 1 || idx->n > INT32_MAX) return fail(c, UHNSW_EINVAL, "n=%lld outside [1, 2^31)", (long long)idx->n);
+    if (idx->d < 1 || idx->d > UHNSW_DMAX) return fail(c, UHNSW_EINVAL, "d=%d outside [1, %d]", idx->d, UHNSW_DMAX);
+    if (idx->storage < UHNSW_STORE_F32 || idx->storage > UHNSW_STORE_F16)
+        return fail(c, UHNSW_EINVAL, "unknown storage %d", idx->storage);
+    for (int i = 0; i < 2; ++i) {
+        int r = check_graph(c, idx->graphs[i], idx->n, i);
+        if (r) return r;
+    }
+    for (int64_t i = 0; i < idx->n * idx->d; ++i)
+        if (!std::isfinite(idx->base[i]))
+            return fail(c, UHNSW_EINVAL, "base value %lld is not finite", (long long)i);
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    c->loaded = false;
+    const int layout = layout_for_dim(idx->d);
+    const LayoutInfo li = layout_info(layout);
+    const int64_t pitch = (int64_t)li.G * li.V * li.NCH;
+    const int64_t n = idx->n;
+    {
+        std::vector<float> rows((size_t)n * pitch, 0.0f);
+        for (int64_t v = 0; v < n; ++v)
+            std::memcpy(&rows[(size_t)v * pitch], idx->base + (size_t)v * idx->d, sizeof(float) * idx->d);
+        HIP_OR_FAIL(c, c->f32_base.ensure(rows.size() * 4));
+        HIP_OR_FAIL(c, hipMemcpy(c->f32_base.p, rows.data(), rows.size() * 4, hipMemcpyHostToDevice));
+    }
+    if (idx->storage != UHNSW_STORE_F32) {
+        HIP_OR_FAIL(c, c->walk_base.ensure((size_t)n * pitch * 2));
+        HIP_OR_FAIL(c, launch_convert(c->f32_base.as<float>(), c->walk_base.p, n * pitch, idx->storage, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    } else {
+        c->walk_base.reset();
+    }
+    for (int i = 0; i < 2; ++i) {
+        int r = upload_graph(c, idx->graphs[i], n, c->g[i]);
+        if (r) return r;
+    }
+    c->n = n;
+    c->d = idx->d;
+    c->storage = idx->storage;
+    c->layout = layout;
+    c->pitch = pitch;
+    c->loaded = true;
+    c->failed = false;
+    return UHNSW_OK;
+}
+
+int uhnsw_get_layout(const uhnsw_ctx *c, int32_t *g, int32_t *v) {
+    if (!c || !g || !v) return UHNSW_EINVAL;
+    if (!c->loaded) return UHNSW_ESTATE;
+    const LayoutInfo li = layout_info(c->layout);
+    *g = li.G;
+    *v = li.V;
+    return UHNSW_OK;
+}
+
+int uhnsw_device_info(const uhnsw_ctx *c_, int32_t *num_cus, int32_t *wall_clock_khz) {
+    uhnsw_ctx *c = const_cast<uhnsw_ctx *>(c_);
+    if (!c || !num_cus || !wall_clock_khz) return UHNSW_EINVAL;
+    int rate = 0;
+    HIP_OR_FAIL(c, hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, c->device));
+    *num_cus = c->num_cus;
+    *wall_clock_khz = rate;
+    return UHNSW_OK;
+}
+
+int uhnsw_last_timing(const uhnsw_ctx *c_, float *walk_ms, float *verify_ms) {
+    uhnsw_ctx *c = const_cast<uhnsw_ctx *>(c_);
+    if (!c || !walk_ms || !verify_ms) return UHNSW_EINVAL;
+    if (!c->timed) return fail(c, UHNSW_ESTATE, "no timed search yet");
+    HIP_OR_FAIL(c, hipEventSynchronize(c->ev[2]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(walk_ms, c->ev[0], c->ev[1]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(verify_ms, c->ev[1], c->ev[2]));
+    return UHNSW_OK;
+}
+
+int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                        float *cand_keys, int32_t c_stride, void *stream) {
+    if (!c) return UHNSW_EINVAL;
+    if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
+    if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
+    if (nq < 0 || nq > INT32_MAX) return fail(c, UHNSW_EINVAL, "nq=%lld outside [0, 2^31)", (long long)nq);
+    if (nq == 0) return UHNSW_OK;
+    if (!queries || !p || !k || !ef || !ids || !dists) return fail(c, UHNSW_EINVAL, "NULL array argument");
+    if (k_max < 1 || k_max > UHNSW_KMAX) return fail(c, UHNSW_EINVAL, "k_max=%d outside [1, %d]", k_max, UHNSW_KMAX);
+    if (ef_max < k_max || ef_max > UHNSW_EFMAX)
+        return fail(c, UHNSW_EINVAL, "ef_max=%d outside [k_max, %d]", ef_max, UHNSW_EFMAX);
+    if (k_stride < k_max) return fail(c, UHNSW_EINVAL, "k_stride=%d < k_max=%d", k_stride, k_max);
+    if ((cand_ids || cand_keys) && (!cand_ids || !cand_keys || c_stride < 1))
+        return fail(c, UHNSW_EINVAL, "candidate output needs both arrays and c_stride >= 1");
+    uhnsw_params prm;
+    if (prm_in)
+        prm = *prm_in;
+    else
+        uhnsw_default_params(&prm);
+    int r = check_params(c, prm);
+    if (r) return r;
+    Plan pl;
+    if ((r = make_plan(c, k_max, ef_max, prm, &pl))) return r;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    if ((r = ensure_mtab(c, prm.tau))) return r;
+
+    // candidate lists: caller's buffers when given, else ours
+    const int32_t cs = cand_ids ? c_stride : ef_max;
+    int32_t *cid = cand_ids;
+    float *ckey = cand_keys;
+    if (!cid) {
+        HIP_OR_FAIL(c, c->cand_ids.ensure((size_t)nq * cs * 4));
+        HIP_OR_FAIL(c, c->cand_keys.ensure((size_t)nq * cs * 4));
+        cid = c->cand_ids.as<int32_t>();
+        ckey = c->cand_keys.as<float>();
+    } else if (c_stride < ef_max) {
+        return fail(c, UHNSW_EINVAL, "c_stride=%d < ef_max=%d", c_stride, ef_max);
+    }
+    HIP_OR_FAIL(c, c->ncand.ensure((size_t)nq * 4));
+    uhnsw_stats *st = stats;
+    if (!st) {
+        HIP_OR_FAIL(c, c->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
+        st = c->stats.as<uhnsw_stats>();
+    }
+
+    SearchArgs a{};
+    a.walk_base = c->storage == UHNSW_STORE_F32 ? c->f32_base.p : c->walk_base.p;
+    a.f32_base = c->f32_base.as<float>();
+    a.pitch = c->pitch;
+    a.n = (int32_t)c->n;
+    a.d = c->d;
+    a.storage = c->storage;
+    for (int i = 0; i < 2; ++i) {
+        a.g[i].adj0 = c->g[i].adj0.as<int32_t>();
+        a.g[i].up_off = c->g[i].up_off.as<int32_t>();
+        a.g[i].up_adj = c->g[i].up_adj.as<int32_t>();
+        a.g[i].entry = c->g[i].entry;
+        a.g[i].max_level = c->g[i].max_level;
+        a.g[i].M = c->g[i].M;
+        a.g[i].M0 = c->g[i].M0;
+    }
+    a.queries = queries;
+    a.p = p;
+    a.k = k;
+    a.ef = ef;
+    a.nq = nq;
+    a.k_max = k_max;
+    a.ef_max = ef_max;
+    a.cutoff = prm.cutoff;
+    a.t_param = prm.t;
+    a.kappa_param = prm.kappa;
+    a.beam = prm.beam_width;
+    a.early_abort = prm.early_abort;
+    a.mtab = c->mtab.as<int32_t>();
+    a.ef_cap = pl.ef_cap;
+    a.vis_bits = pl.vis_bits;
+    a.kv_cap = pl.kv_cap;
+    a.waves_per_block = pl.wpb;
+    a.cand_ids = cid;
+    a.cand_keys = ckey;
+    a.c_stride = cs;
+    a.ncand = c->ncand.as<int32_t>();
+    a.ids = ids;
+    a.dists = dists;
+    a.k_stride = k_stride;
+    a.stats = st;
+    a.counter = nullptr;
+
+    const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
+    int walk_grid = grid_all;
+    if (prm.persistent) {
+        HIP_OR_FAIL(c, c->counter.ensure(4));
+        a.counter = c->counter.as<int32_t>();
+        int per_cu = 0;
+        HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(c->layout), pl.wpb * kWave,
+                                                                    (size_t)pl.walk_bytes * pl.wpb));
+        walk_grid = std::max(1, std::min(grid_all, per_cu * c->num_cus));
+        HIP_OR_FAIL(c, launch_fill_i32(a.counter, 0, 1, s));
+    }
+    c->timed = prm.timing != 0;
+    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], s));
+    a.lds_wave_bytes = pl.walk_bytes;
+    HIP_OR_FAIL(c, launch_walk(a, c->layout, walk_grid, s));
+    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[1], s));
+    a.lds_wave_bytes = pl.verify_bytes;
+    a.counter = nullptr;
+    HIP_OR_FAIL(c, launch_verify(a, c->layout, grid_all, s));
+    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[2], s));
+    return UHNSW_OK;
+}
+
+int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                 const int32_t *ef, const uhnsw_params *prm, int32_t k_stride, int64_t *ids, float *dists,
+                 uhnsw_stats *stats) {
+    if (!c) return UHNSW_EINVAL;
+    if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
+    if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
+    if (nq < 0 || nq > INT32_MAX) return fail(c, UHNSW_EINVAL, "nq=%lld outside [0, 2^31)", (long long)nq);
+    if (nq == 0) return UHNSW_OK;
+    if (!queries || !p || !k || !ef || !ids || !dists) return fail(c, UHNSW_EINVAL, "NULL array argument");
+    int k_max = 0, ef_max = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        if (!std::isfinite(p[i]) || p[i] < 0.5f || p[i] > 2.0f)
+            return fail(c, UHNSW_EINVAL, "p[%lld]=%g outside [0.5, 2]", (long long)i, (double)p[i]);
+        if (k[i] < 1 || k[i] > UHNSW_KMAX)
+            return fail(c, UHNSW_EINVAL, "k[%lld]=%d outside [1, %d]", (long long)i, k[i], UHNSW_KMAX);
+        if (ef[i] < k[i] || ef[i] > UHNSW_EFMAX)
+            return fail(c, UHNSW_EINVAL, "ef[%lld]=%d outside [k, %d]", (long long)i, ef[i], UHNSW_EFMAX);
+        k_max = std::max(k_max, k[i]);
+        ef_max = std::max(ef_max, ef[i]);
+    }
+    for (int64_t i = 0; i < nq * c->d; ++i)
+        if (!std::isfinite(queries[i]))
+            return fail(c, UHNSW_EINVAL, "query value %lld is not finite", (long long)i);
+    if (k_stride < k_max) return fail(c, UHNSW_EINVAL, "k_stride=%d < max k=%d", k_stride, k_max);
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    const size_t nqs = (size_t)nq;
+    HIP_OR_FAIL(c, c->s_q.ensure(nqs * c->d * 4));
+    HIP_OR_FAIL(c, c->s_p.ensure(nqs * 4));
+    HIP_OR_FAIL(c, c->s_k.ensure(nqs * 4));
+    HIP_OR_FAIL(c, c->s_ef.ensure(nqs * 4));
+    HIP_OR_FAIL(c, c->s_ids.ensure(nqs * k_stride * 8));
+    HIP_OR_FAIL(c, c->s_dists.ensure(nqs * k_stride * 4));
+    HIP_OR_FAIL(c, c->s_stats.ensure(nqs * sizeof(uhnsw_stats)));
+    hipStream_t s = c->stream;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_q.p, queries, nqs * c->d * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_p.p, p, nqs * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_k.p, k, nqs * 4, hipMemcpyHostToDevice, s));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_ef.p, ef, nqs * 4, hipMemcpyHostToDevice, s));
+    int r = uhnsw_search_device(c, c->s_q.as<float>(), nq, c->s_p.as<float>(), c->s_k.as<int32_t>(),
+                                c->s_ef.as<int32_t>(), k_max, ef_max, prm, k_stride, c->s_ids.as<int64_t>(),
+                                c->s_dists.as<float>(), c->s_stats.as<uhnsw_stats>(), nullptr, nullptr, 0, s);
+    if (r) return r;
+    HIP_OR_FAIL(c, hipMemcpyAsync(ids, c->s_ids.p, nqs * k_stride * 8, hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(c, hipMemcpyAsync(dists, c->s_dists.p, nqs * k_stride * 4, hipMemcpyDeviceToHost, s));
+    if (stats) HIP_OR_FAIL(c, hipMemcpyAsync(stats, c->s_stats.p, nqs * sizeof(uhnsw_stats), hipMemcpyDeviceToHost, s));
+    HIP_OR_FAIL(c, hipStreamSynchronize(s));
+    return UHNSW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Internal structures shared by the host side and the kernels of libuhnsw.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "uhnsw.h"
+
+namespace uhnsw {
+
+constexpr int kWave = 64;
+constexpr int kUCap = 64;            // neighbours gathered per walk step (beam_width * M0)
+constexpr uint32_t kExpBit = 0x80000000u;
+constexpr uint32_t kIdMask = 0x7fffffffu;
+
+// Row layout of one stored vector: element j is read by lane (j / V) % G of
+// a G-lane group, in chunk j / (G * V); NCH chunks cover the padded row.
+enum LayoutId : int { L8x4x1 = 0, L8x4x2, L8x4x4, L16x4x4, L32x4x4, L64x4x4, kNumLayouts };
+
+struct LayoutInfo {
+    int G, V, NCH;
+};
+inline LayoutInfo layout_info(int id) {
+    static const LayoutInfo t[kNumLayouts] = {{8, 4, 1}, {8, 4, 2}, {8, 4, 4}, {16, 4, 4}, {32, 4, 4}, {64, 4, 4}};
+    return t[id];
+}
+inline int layout_for_dim(int d) {
+    if (d <= 32) return L8x4x1;
+    if (d <= 64) return L8x4x2;
+    if (d <= 128) return L8x4x4;
+    if (d <= 256) return L16x4x4;
+    if (d <= 512) return L32x4x4;
+    return L64x4x4;
+}
+
+struct DevGraph {
+    const int32_t *adj0;    // [n * M0], -1 padded
+    const int32_t *up_off;  // [n], row in up_adj of the node's layer 1, -1 on level-0 nodes
+    const int32_t *up_adj;  // [rows * M], -1 padded, valid ids first
+    int32_t entry, max_level, M, M0;
+};
+
+struct SearchArgs {
+    // index
+    const void *walk_base;  // walk rows (storage type), pitch elements each
+    const float *f32_base;  // FP32 rows for verification
+    int64_t pitch;          // elements per row (both copies share it)
+    int32_t n, d, storage;
+    DevGraph g[2];
+    // queries
+    const float *queries;   // [nq x d]
+    const float *p;
+    const int32_t *k;
+    const int32_t *ef;
+    int64_t nq;
+    int32_t k_max, ef_max;
+    // Algorithm 1 parameters
+    float cutoff;
+    int32_t t_param, kappa_param, beam, early_abort;
+    const int32_t *mtab;    // [UHNSW_KMAX + 1]: ceil(tau * K)
+    // LDS plan (per wave)
+    int32_t ef_cap, vis_bits, kv_cap, lds_wave_bytes, waves_per_block;
+    // candidate lists (walk -> verify)
+    int32_t *cand_ids;
+    float *cand_keys;
+    int32_t c_stride;
+    int32_t *ncand;         // [nq]
+    // outputs
+    int64_t *ids;
+    float *dists;
+    int32_t k_stride;
+    uhnsw_stats *stats;
+    // persistent scheduling
+    int32_t *counter;       // nullptr: one wave per query by grid position
+};
+
+// Launchers (uhnsw_kernels.hip). Return the HIP status of the launch.
+hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s);
+hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
+int walk_lds_bytes(int ef_cap, int vis_bits);
+int verify_lds_bytes(int kv_cap);
+const void *walk_kernel_ptr(int layout);
+const void *verify_kernel_ptr(int layout);
+
+}  // namespace uhnsw

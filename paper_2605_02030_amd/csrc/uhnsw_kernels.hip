@@ -1,0 +1,806 @@
+// gfx950 kernels of the U-HNSW query path (U-HNSW paper, Sec. 3.1 and
+// Algorithm 1). One 64-lane wavefront serves one query; each wave keeps its
+// state in its own slice of LDS, so waves of one workgroup never wait for
+// each other.
+//
+//   walk   : graph choice, greedy descent over the upper layers, layer-0
+//            best-first search with the sorted candidate list W in LDS, C out.
+//   verify : batched L_p verification of C with the tau early stop.
+//
+// Base distances follow one fixed FP32 order: element j is accumulated by
+// lane (j / V) % G of a G-lane group in ascending j (L2 by fused
+// multiply-add), and the G lanes combine pairwise (lane l < o takes
+// s_l + s_{l+o}, o = G/2 .. 1). Rows are zero-padded to G*V*NCH elements,
+// which adds exact zeros only.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "uhnsw_internal.h"
+
+namespace uhnsw {
+
+// ------------------------------------------------------------ wave helpers
+// Orders this wave's LDS accesses across lanes: LDS operations of one wave
+// execute in program order, so a compiler-level fence is all that is needed.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool b) { return __ballot(b); }
+
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ bool key_less(float ka, uint32_t ia, float kb, uint32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+// Pairwise combine inside a G-lane group; lane l < o receives s_l + s_{l+o}.
+template <int G>
+__device__ __forceinline__ float group_sum(float s) {
+#pragma unroll
+    for (int o = G / 2; o >= 1; o >>= 1) s = s + __shfl_xor(s, o, kWave);
+    return s;
+}
+
+// Wave-wide minimum of (key, id); every lane gets the result.
+__device__ __forceinline__ void wave_argmin(float &k, int32_t &id) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        float ko = __shfl_xor(k, o, kWave);
+        int32_t io = __shfl_xor(id, o, kWave);
+        if (key_less(ko, (uint32_t)io, k, (uint32_t)id)) {
+            k = ko;
+            id = io;
+        }
+    }
+}
+
+// ------------------------------------------------------- element loading
+template <typename T>
+struct Elem;
+template <>
+struct Elem<float> {
+    __device__ static __forceinline__ void load4(const float *p, float (&x)[4]) {
+        float4 v = *reinterpret_cast<const float4 *>(p);
+        x[0] = v.x;
+        x[1] = v.y;
+        x[2] = v.z;
+        x[3] = v.w;
+    }
+};
+struct bf16_t {
+    uint16_t b;
+};
+struct f16_t {
+    uint16_t b;
+};
+template <>
+struct Elem<bf16_t> {
+    __device__ static __forceinline__ void load4(const bf16_t *p, float (&x)[4]) {
+        uint2 v = *reinterpret_cast<const uint2 *>(p);
+        x[0] = __uint_as_float(v.x << 16);
+        x[1] = __uint_as_float(v.x & 0xffff0000u);
+        x[2] = __uint_as_float(v.y << 16);
+        x[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+template <>
+struct Elem<f16_t> {
+    __device__ static __forceinline__ void load4(const f16_t *p, float (&x)[4]) {
+        uint2 v = *reinterpret_cast<const uint2 *>(p);
+        x[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
+        x[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
+        x[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
+        x[3] = __half2float(__ushort_as_half((unsigned short)(v.y >> 16)));
+    }
+};
+
+// ----------------------------------------------------------- base metric
+// keys[r] = delta(row ids[r], q) for r < nrows. All lanes must call. The
+// loads of up to RB row-steps are issued before any arithmetic so that a
+// whole neighbour list is in flight at once.
+template <int G, int NCH, typename T, bool L1>
+__device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64_t pitch,
+                                               const int32_t *ids, int nrows, const float (&qv)[NCH][4],
+                                               float *keys) {
+    constexpr int V = 4;
+    constexpr int RPW = kWave / G;
+    constexpr int RB = (64 / (NCH * V)) > 0 ? (64 / (NCH * V)) : 1;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
+        float x[RB][NCH][V];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const int row = r0 + b * RPW + grp;
+            if (row < nrows) {
+                const T *rp = base + (int64_t)ids[row] * pitch + gl * V;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) Elem<T>::load4(rp + c * G * V, x[b][c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) x[b][c][e] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const float dlt = x[b][c][e] - qv[c][e];
+                    if (L1)
+                        s = s + fabsf(dlt);
+                    else
+                        s = __builtin_fmaf(dlt, dlt, s);
+                }
+            s = group_sum<G>(s);
+            const int row = r0 + b * RPW + grp;
+            if (row < nrows && gl == 0) keys[row] = s;
+        }
+    }
+}
+
+template <int G, int NCH, typename T>
+__device__ __forceinline__ void base_dists(bool l1, const T *base, int64_t pitch, const int32_t *ids, int nrows,
+                                           const float (&qv)[NCH][4], float *keys) {
+    if (l1)
+        rows_base_dist<G, NCH, T, true>(base, pitch, ids, nrows, qv, keys);
+    else
+        rows_base_dist<G, NCH, T, false>(base, pitch, ids, nrows, qv, keys);
+}
+
+// --------------------------------------------------- sorted-list insert
+// L (keys Lk, ids Li; ids may carry kExpBit) holds nL entries ascending by
+// (key, id). Insert the nU entries of (Uk, Ui) (any order, ids without the
+// bit), drop those already present, keep the first cap entries. Scratch:
+// Ulo, Urank, Slo, each nU ints. Returns the new size; *min_new receives the
+// smallest position any new entry took (cap if none); *n_in the number of
+// new entries now in L. With dedupe_u, an id listed twice in U is kept once
+// (U holds at most kUCap entries then).
+__device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const float *Uk, const int32_t *Ui,
+                                 int nU, int32_t *Ulo, int32_t *Urank, int32_t *Slo, bool dedupe_u, int *min_new,
+                                 int *n_in) {
+    const int lane = lane_id();
+    // 1. insertion point of each candidate; -1 marks a duplicate
+    for (int u = lane; u < nU; u += kWave) {
+        const float uk = Uk[u];
+        const uint32_t ui = (uint32_t)Ui[u];
+        int lo = 0, hi = nL;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key_less(Lk[mid], Li[mid] & kIdMask, uk, ui))
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const bool dup = lo < nL && (Li[lo] & kIdMask) == ui;
+        Ulo[u] = (dup || lo >= cap) ? -1 : lo;
+    }
+    wave_sync();
+    if (dedupe_u) {  // keep the first copy of an id listed twice in U
+        bool drop[(kUCap + kWave - 1) / kWave] = {};
+        for (int u0 = 0, w = 0; u0 < nU && w < (kUCap + kWave - 1) / kWave; u0 += kWave, ++w) {
+            const int u = u0 + lane;
+            if (u < nU && Ulo[u] >= 0)
+                for (int j = 0; j < u; ++j)
+                    if (Ui[j] == Ui[u]) drop[w] = true;
+        }
+        wave_sync();
+        for (int u0 = 0, w = 0; u0 < nU && w < (kUCap + kWave - 1) / kWave; u0 += kWave, ++w)
+            if (u0 + lane < nU && drop[w]) Ulo[u0 + lane] = -1;
+        wave_sync();
+    }
+    // 2. rank among the kept candidates
+    int nkeep = 0;
+    for (int u0 = 0; u0 < nU; u0 += kWave) {
+        const int u = u0 + lane;
+        int rank = -1;
+        bool kept = false;
+        if (u < nU && Ulo[u] >= 0) {
+            kept = true;
+            const float uk = Uk[u];
+            const uint32_t ui = (uint32_t)Ui[u];
+            rank = 0;
+            for (int j = 0; j < nU; ++j)
+                if (Ulo[j] >= 0 && key_less(Uk[j], (uint32_t)Ui[j], uk, ui)) ++rank;
+        }
+        if (u < nU) Urank[u] = rank;
+        nkeep += popc64(ballot(kept));
+    }
+    wave_sync();
+    *n_in = 0;
+    *min_new = cap;
+    if (nkeep == 0) return nL;
+    for (int u = lane; u < nU; u += kWave)
+        if (Urank[u] >= 0) Slo[Urank[u]] = Ulo[u];
+    wave_sync();
+    const int first = Slo[0];
+    // 3. move the old entries at positions >= first to the right, top chunk first
+    for (int cs = ((nL - 1) / kWave) * kWave; cs >= 0 && cs + kWave > first; cs -= kWave) {
+        const int i = cs + lane;
+        const bool act = i >= first && i < nL;
+        float k = 0.0f;
+        uint32_t id = 0;
+        int ni = cap;
+        if (act) {
+            k = Lk[i];
+            id = Li[i];
+            int a = 0, b = nkeep;
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (Slo[m] <= i)
+                    a = m + 1;
+                else
+                    b = m;
+            }
+            ni = i + a;
+        }
+        wave_sync();
+        if (act && ni < cap) {
+            Lk[ni] = k;
+            Li[ni] = id;
+        }
+        wave_sync();
+    }
+    // 4. place the new entries
+    int nin = 0;
+    for (int u0 = 0; u0 < nU; u0 += kWave) {
+        const int u = u0 + lane;
+        bool in = false;
+        if (u < nU && Urank[u] >= 0) {
+            const int np = Ulo[u] + Urank[u];
+            if (np < cap) {
+                Lk[np] = Uk[u];
+                Li[np] = (uint32_t)Ui[u];
+                in = true;
+            }
+        }
+        nin += popc64(ballot(in));
+    }
+    wave_sync();
+    *n_in = nin;
+    *min_new = first;
+    const int nn = nL + nkeep;
+    return nn < cap ? nn : cap;
+}
+
+__device__ __forceinline__ uint32_t vis_slot(int32_t id, int bits) {
+    return ((uint32_t)id * 2654435761u) >> (32 - bits);
+}
+
+// ------------------------------------------------------------------- walk
+struct WalkLds {
+    float *Wk;
+    uint32_t *Wi;
+    int32_t *vis;
+    int32_t *Uid;
+    float *Uk;
+    int32_t *Ulo, *Urank, *Slo;
+};
+
+__host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits) {
+    return ef_cap * 8 + (1 << vis_bits) * 4 + kUCap * 4 * 5;
+}
+
+__device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits) {
+    WalkLds L;
+    L.Wk = reinterpret_cast<float *>(p);
+    L.Wi = reinterpret_cast<uint32_t *>(L.Wk + ef_cap);
+    L.vis = reinterpret_cast<int32_t *>(L.Wi + ef_cap);
+    L.Uid = L.vis + (1 << vis_bits);
+    L.Uk = reinterpret_cast<float *>(L.Uid + kUCap);
+    L.Ulo = reinterpret_cast<int32_t *>(L.Uk + kUCap);
+    L.Urank = L.Ulo + kUCap;
+    L.Slo = L.Urank + kUCap;
+    return L;
+}
+
+__device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, int ef) {
+    return !(p >= 0.5f && p <= 2.0f) || K < 1 || K > A.k_max || K > UHNSW_KMAX || ef < K || ef > A.ef_max ||
+           ef > A.ef_cap;
+}
+
+template <int G, int NCH, typename T>
+__device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
+    const int lane = lane_id();
+    const uint32_t t_begin = (uint32_t)wall_clock64();
+    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits);
+    const float p = A.p[qi];
+    const int K = A.k[qi];
+    const int ef = A.ef[qi];
+    uhnsw_stats *st = A.stats + qi;
+    int32_t *cid = A.cand_ids + qi * A.c_stride;
+    float *ckey = A.cand_keys + qi * A.c_stride;
+    bool finite = true;
+    for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
+    const bool bad = query_bad(A, p, K, ef) || ballot(!finite) != 0;
+    if (bad) {
+        for (int i = lane; i < A.c_stride; i += kWave) {
+            cid[i] = -1;
+            ckey[i] = INFINITY;
+        }
+        if (lane == 0) {
+            A.ncand[qi] = -1;
+            st->graph = 0;
+            st->n_b = st->n_exp = st->n_p = st->batches = st->nc = 0;
+            st->flags = UHNSW_QBAD;
+            st->entry0 = -1;
+            st->t_begin = st->t_end = t_begin;
+        }
+        return;
+    }
+    const int gsel = (p <= A.cutoff) ? 0 : 1;
+    const DevGraph &Gr = A.g[gsel];
+    const bool l1 = gsel == 0;
+    const int tp = A.t_param > 0 ? A.t_param : 6 * K;
+    int t = ef < tp ? ef : tp;
+    if (t < K) t = K;
+    const T *base = reinterpret_cast<const T *>(A.walk_base);
+    const int64_t pitch = A.pitch;
+
+    // query slice of this lane, zero beyond d
+    float qv[NCH][4];
+    {
+        const int gl = lane % G;
+        const float *q = A.queries + qi * A.d;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = c * G * 4 + gl * 4 + e;
+                qv[c][e] = j < A.d ? q[j] : 0.0f;
+            }
+    }
+    const int vslots = 1 << A.vis_bits;
+    for (int i = lane; i < vslots; i += kWave) L.vis[i] = -1;
+
+    // ---- descent over layers max_level .. 1 (greedy, smallest (key, id))
+    int32_t cur = Gr.entry;
+    if (lane == 0) L.Uid[0] = cur;
+    wave_sync();
+    base_dists<G, NCH, T>(l1, base, pitch, L.Uid, 1, qv, L.Uk);
+    wave_sync();
+    float kcur = L.Uk[0];
+    int n_b = 1;
+    for (int l = Gr.max_level; l >= 1; --l) {
+        for (;;) {
+            wave_sync();
+            const int64_t row = (int64_t)Gr.up_off[cur] + (l - 1);
+            const int32_t nb = lane < Gr.M ? Gr.up_adj[row * Gr.M + lane] : -1;
+            const int cnt = popc64(ballot(nb >= 0));
+            if (nb >= 0) L.Uid[lane] = nb;  // valid ids come first in each row
+            wave_sync();
+            base_dists<G, NCH, T>(l1, base, pitch, L.Uid, cnt, qv, L.Uk);
+            wave_sync();
+            n_b += cnt;
+            float kb = lane < cnt ? L.Uk[lane] : INFINITY;
+            int32_t ib = lane < cnt ? L.Uid[lane] : 0x7fffffff;
+            wave_argmin(kb, ib);
+            if (cnt > 0 && key_less(kb, (uint32_t)ib, kcur, (uint32_t)cur)) {
+                cur = ib;
+                kcur = kb;
+            } else {
+                break;
+            }
+        }
+    }
+    const int32_t entry0 = cur;
+
+    // ---- layer 0: best-first expansion of the sorted list W
+    wave_sync();
+    if (lane == 0) {
+        L.Wk[0] = kcur;
+        L.Wi[0] = (uint32_t)cur;
+        L.vis[vis_slot(cur, A.vis_bits)] = cur;
+    }
+    wave_sync();
+    int nW = 1, lb = 0, n_exp = 0, flags = 0;
+    const int M0 = Gr.M0;
+    const int beam = A.beam;
+    for (;;) {
+        // the first `beam` (1 or 2) unexpanded entries, scanning from lb;
+        // all values here are wave-uniform (LDS broadcast reads)
+        int npick = 0, pos0 = -1, pos1 = -1;
+        uint32_t node0 = 0, node1 = 0;
+        for (int b0 = lb; b0 < nW && npick < beam; b0 += kWave) {
+            const int i = b0 + lane;
+            const bool un = i < nW && !(L.Wi[i] & kExpBit);
+            uint64_t m = ballot(un);
+            while (m && npick < beam) {
+                const int pos = b0 + __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                if (npick == 0) {
+                    pos0 = pos;
+                    node0 = L.Wi[pos];
+                } else {
+                    pos1 = pos;
+                    node1 = L.Wi[pos];
+                }
+                ++npick;
+            }
+        }
+        if (npick == 0) break;
+        if (n_exp >= A.n) {  // a valid walk expands each node at most once
+            flags |= UHNSW_QCAP;
+            break;
+        }
+        lb = pos0;
+        wave_sync();
+        if (lane == 0) {
+            L.Wi[pos0] = node0 | kExpBit;
+            if (npick > 1) L.Wi[pos1] = node1 | kExpBit;
+        }
+        n_exp += npick;
+        // neighbours: lane = slot `lane % M0` of picked node `lane / M0`
+        const int which = lane / M0, slot = lane % M0;
+        int32_t nb = -1;
+        if (which < npick) nb = Gr.adj0[(int64_t)(which == 0 ? node0 : node1) * M0 + slot];
+        bool fresh = false;
+        uint32_t vs = 0;
+        if (nb >= 0) {
+            vs = vis_slot(nb, A.vis_bits);
+            fresh = L.vis[vs] != nb;
+        }
+        wave_sync();
+        if (fresh) L.vis[vs] = nb;
+        const uint64_t fm = ballot(fresh);
+        const int nnew = popc64(fm);
+        if (nnew == 0) continue;
+        if (fresh) L.Uid[lanes_below(fm)] = nb;
+        wave_sync();
+        base_dists<G, NCH, T>(l1, base, pitch, L.Uid, nnew, qv, L.Uk);
+        wave_sync();
+        n_b += nnew;
+        int min_new, n_in;
+        nW = merge_into_sorted(L.Wk, L.Wi, nW, ef, L.Uk, L.Uid, nnew, L.Ulo, L.Urank, L.Slo, npick > 1, &min_new,
+                               &n_in);
+        if (min_new < lb) lb = min_new;
+    }
+
+    // ---- C = first t of W
+    const int nc = nW < t ? nW : t;
+    for (int i = lane; i < A.c_stride; i += kWave) {
+        cid[i] = i < nc ? (int32_t)(L.Wi[i] & kIdMask) : -1;
+        ckey[i] = i < nc ? L.Wk[i] : INFINITY;
+    }
+    if (lane == 0) {
+        A.ncand[qi] = nc;
+        st->graph = gsel + 1;
+        st->n_b = n_b;
+        st->n_exp = n_exp;
+        st->nc = nc;
+        st->flags = flags;
+        st->entry0 = entry0;
+        st->t_begin = t_begin;
+    }
+}
+
+// Next query index for this wave from the work counter. Every lane issues
+// the atomic (lane 0 adds 1, the others add 0) so that no lane-dependent
+// branch precedes the broadcast; the broadcast takes lane 0's old value.
+__device__ __forceinline__ int fetch_query(int32_t *counter) {
+    const int v = atomicAdd(counter, lane_id() == 0 ? 1 : 0);
+    return __builtin_amdgcn_readfirstlane(__shfl(v, 0, kWave));
+}
+
+template <int G, int NCH, typename T>
+__device__ __noinline__ void walk_query(const SearchArgs &A, int64_t qi, char *lds) {
+    walk_one<G, NCH, T>(A, qi, lds);
+}
+
+template <int G, int NCH, typename T>
+__global__ void __launch_bounds__(256) walk_kernel(SearchArgs A) {
+    extern __shared__ char lds_all[];
+    const int wave = threadIdx.x / kWave;
+    char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
+    if (A.counter == nullptr) {
+        const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
+        if (qi < A.nq) walk_one<G, NCH, T>(A, qi, lds);
+        return;
+    }
+    // persistent: waves take queries from the counter until it passes nq
+    int qi = fetch_query(A.counter);
+    while ((int64_t)qi < A.nq) {
+        walk_query<G, NCH, T>(A, qi, lds);
+        qi = fetch_query(A.counter);
+    }
+}
+
+// ----------------------------------------------------------------- verify
+// L_p term |dlt|^p by class: 1 -> p = 1, 2 -> p = 2, 3 -> p = 0.5,
+// 4 -> p = 1.5 (square roots, the paper's second cost class, Sec. 2.1),
+// 0 -> any other p as exp2(p * log2|dlt|) on v_log_f32 / v_exp_f32.
+template <int PC>
+__device__ __forceinline__ float lp_acc(float s, float dlt, float p) {
+    const float a = fabsf(dlt);
+    if (PC == 1) return s + a;
+    if (PC == 2) return __builtin_fmaf(dlt, dlt, s);
+    if (PC == 3) return s + __builtin_amdgcn_sqrtf(a);
+    if (PC == 4) return __builtin_fmaf(a, __builtin_amdgcn_sqrtf(a), s);
+    return s + __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(a));
+}
+
+// S[r] = sum |x - q|^p for the FP32 rows ids[r]; with abort set, S > thr is
+// reported as +inf (such a row cannot enter the top K).
+template <int G, int NCH, int PC>
+__device__ __forceinline__ void rows_lp(const float *__restrict__ base, int64_t pitch, const int32_t *ids,
+                                        int nrows, const float (&qv)[NCH][4], float p, float thr, bool abort,
+                                        float *S) {
+    constexpr int V = 4;
+    constexpr int RPW = kWave / G;
+    constexpr int RB = (64 / (NCH * V)) > 0 ? (64 / (NCH * V)) : 1;
+    const int lane = lane_id();
+    const int grp = lane / G, gl = lane % G;
+    for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
+        float x[RB][NCH][V];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const int row = r0 + b * RPW + grp;
+            if (row < nrows) {
+                const float *rp = base + (int64_t)ids[row] * pitch + gl * V;
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) Elem<float>::load4(rp + c * G * V, x[b][c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) x[b][c][e] = qv[c][e];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c)
+#pragma unroll
+                for (int e = 0; e < V; ++e) s = lp_acc<PC>(s, x[b][c][e] - qv[c][e], p);
+            s = group_sum<G>(s);
+            const int row = r0 + b * RPW + grp;
+            if (row < nrows && gl == 0) S[row] = (abort && s > thr) ? INFINITY : s;
+        }
+    }
+}
+
+template <int G, int NCH>
+__device__ __forceinline__ void lp_dists(int pc, const float *base, int64_t pitch, const int32_t *ids, int nrows,
+                                         const float (&qv)[NCH][4], float p, float thr, bool abort, float *S) {
+    switch (pc) {
+        case 1: rows_lp<G, NCH, 1>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+        case 2: rows_lp<G, NCH, 2>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+        case 3: rows_lp<G, NCH, 3>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+        case 4: rows_lp<G, NCH, 4>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+        default: rows_lp<G, NCH, 0>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+    }
+}
+
+__device__ __forceinline__ float lp_root(float S, float p, int pc) {
+    if (pc == 1) return S;
+    if (pc == 2) return sqrtf(S);
+    if (pc == 3) return S * S;
+    if (!(S > 0.0f)) return S;
+    return exp2f(log2f(S) / p);
+}
+
+struct VerifyLds {
+    float *Rk;
+    uint32_t *Ri;
+    float *Bk;
+    int32_t *Bi;
+    int32_t *Ulo, *Urank, *Slo;
+};
+
+__host__ __device__ inline int verify_lds_bytes_impl(int kv_cap) { return kv_cap * 8 + kv_cap * 8 + kv_cap * 12; }
+
+__device__ inline VerifyLds verify_lds(char *p, int kv_cap) {
+    VerifyLds L;
+    L.Rk = reinterpret_cast<float *>(p);
+    L.Ri = reinterpret_cast<uint32_t *>(L.Rk + kv_cap);
+    L.Bk = reinterpret_cast<float *>(L.Ri + kv_cap);
+    L.Bi = reinterpret_cast<int32_t *>(L.Bk + kv_cap);
+    L.Ulo = L.Bi + kv_cap;
+    L.Urank = L.Ulo + kv_cap;
+    L.Slo = L.Urank + kv_cap;
+    return L;
+}
+
+template <int G, int NCH>
+__device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
+    const int lane = lane_id();
+    const float p = A.p[qi];
+    const int K = A.k[qi];
+    const int ef = A.ef[qi];
+    int64_t *oid = A.ids + qi * A.k_stride;
+    float *odist = A.dists + qi * A.k_stride;
+    uhnsw_stats *st = A.stats + qi;
+    const int nc = A.ncand[qi];
+    if (nc < 0) {  // rejected by the walk
+        for (int r = lane; r < A.k_stride; r += kWave) {
+            oid[r] = -1;
+            odist[r] = INFINITY;
+        }
+        return;
+    }
+    (void)ef;
+    const int kappa = A.kappa_param > 0 ? A.kappa_param : (K > 2 ? K : 2);
+    const VerifyLds L = verify_lds(lds, A.kv_cap);
+    const int pc = p == 1.0f ? 1 : p == 2.0f ? 2 : p == 0.5f ? 3 : p == 1.5f ? 4 : 0;
+    const int m = A.mtab[K];
+    const int32_t *C = A.cand_ids + qi * A.c_stride;
+    float qv[NCH][4];
+    {
+        const int gl = lane % G;
+        const float *q = A.queries + qi * A.d;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = c * G * 4 + gl * 4 + e;
+                qv[c][e] = j < A.d ? q[j] : 0.0f;
+            }
+    }
+    // R = first K of C
+    const int nR = nc < K ? nc : K;
+    for (int i = lane; i < nR; i += kWave) L.Bi[i] = C[i];
+    wave_sync();
+    lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nR, qv, p, 0.0f, false, L.Bk);
+    wave_sync();
+    int dummy_min, dummy_in;
+    int nr = merge_into_sorted(L.Rk, L.Ri, 0, K, L.Bk, L.Bi, nR, L.Ulo, L.Urank, L.Slo, false, &dummy_min,
+                               &dummy_in);
+    int pos = nR, batches = 0;
+    while (pos < nc) {
+        const int nb = nc - pos < kappa ? nc - pos : kappa;
+        const float thr = L.Rk[nr - 1];
+        wave_sync();
+        for (int i = lane; i < nb; i += kWave) L.Bi[i] = C[pos + i];
+        wave_sync();
+        lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nb, qv, p, thr, A.early_abort != 0, L.Bk);
+        wave_sync();
+        // entries at +inf were aborted: move them out of the merge by id order
+        int n_in = 0, min_new;
+        nr = merge_into_sorted(L.Rk, L.Ri, nr, K, L.Bk, L.Bi, nb, L.Ulo, L.Urank, L.Slo, false, &min_new, &n_in);
+        pos += nb;
+        ++batches;
+        if (nr - n_in >= m) break;
+    }
+    wave_sync();
+    for (int r = lane; r < A.k_stride; r += kWave) {
+        if (r < nr) {
+            oid[r] = (int64_t)(L.Ri[r] & kIdMask);
+            odist[r] = lp_root(L.Rk[r], p, pc);
+        } else {
+            oid[r] = -1;
+            odist[r] = INFINITY;
+        }
+    }
+    if (lane == 0) {
+        st->n_p = pos;
+        st->batches = batches;
+        st->t_end = (uint32_t)wall_clock64();
+    }
+}
+
+template <int G, int NCH>
+__global__ void __launch_bounds__(256) verify_kernel(SearchArgs A) {
+    extern __shared__ char lds_all[];
+    const int wave = threadIdx.x / kWave;
+    char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
+    const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
+    if (qi < A.nq) verify_one<G, NCH>(A, qi, lds);
+}
+
+// ------------------------------------------------------------- utilities
+__global__ void fill_i32_kernel(int32_t *dst, int32_t v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+// FP32 -> bfloat16 / binary16, round to nearest even.
+__global__ void convert_kernel(const float *src, uint16_t *dst, int64_t count, int storage) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float f = src[i];
+    if (storage == UHNSW_STORE_BF16) {
+        const uint32_t u = __float_as_uint(f);
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            dst[i] = (uint16_t)((u >> 16) | 0x40u);
+        } else {
+            const uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+            dst[i] = (uint16_t)(r >> 16);
+        }
+    } else {
+        dst[i] = __half_as_ushort(__float2half_rn(f));
+    }
+}
+
+// ---------------------------------------------------------------- launch
+#define UHNSW_LAYOUT_SWITCH(layout, MACRO) \
+    switch (layout) {                      \
+        case L8x4x1: MACRO(8, 1); break;   \
+        case L8x4x2: MACRO(8, 2); break;   \
+        case L8x4x4: MACRO(8, 4); break;   \
+        case L16x4x4: MACRO(16, 4); break; \
+        case L32x4x4: MACRO(32, 4); break; \
+        case L64x4x4: MACRO(64, 4); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s) {
+    const dim3 blk(a.waves_per_block * kWave);
+    const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
+#define W_LAUNCH(G, NCH)                                                                           \
+    if (a.storage == UHNSW_STORE_F32)                                                             \
+        hipLaunchKernelGGL((walk_kernel<G, NCH, float>), dim3(grid), blk, lds, s, a);             \
+    else if (a.storage == UHNSW_STORE_BF16)                                                       \
+        hipLaunchKernelGGL((walk_kernel<G, NCH, bf16_t>), dim3(grid), blk, lds, s, a);            \
+    else                                                                                          \
+        hipLaunchKernelGGL((walk_kernel<G, NCH, f16_t>), dim3(grid), blk, lds, s, a);
+    UHNSW_LAYOUT_SWITCH(layout, W_LAUNCH)
+#undef W_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s) {
+    const dim3 blk(a.waves_per_block * kWave);
+    const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
+#define V_LAUNCH(G, NCH) hipLaunchKernelGGL((verify_kernel<G, NCH>), dim3(grid), blk, lds, s, a);
+    UHNSW_LAYOUT_SWITCH(layout, V_LAUNCH)
+#undef V_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(convert_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src,
+                       reinterpret_cast<uint16_t *>(dst), count, storage);
+    return hipGetLastError();
+}
+
+int walk_lds_bytes(int ef_cap, int vis_bits) { return walk_lds_bytes_impl(ef_cap, vis_bits); }
+int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
+
+const void *walk_kernel_ptr(int layout) {
+    switch (layout) {
+        case L8x4x1: return reinterpret_cast<const void *>(&walk_kernel<8, 1, float>);
+        case L8x4x2: return reinterpret_cast<const void *>(&walk_kernel<8, 2, float>);
+        case L8x4x4: return reinterpret_cast<const void *>(&walk_kernel<8, 4, float>);
+        case L16x4x4: return reinterpret_cast<const void *>(&walk_kernel<16, 4, float>);
+        case L32x4x4: return reinterpret_cast<const void *>(&walk_kernel<32, 4, float>);
+        default: return reinterpret_cast<const void *>(&walk_kernel<64, 4, float>);
+    }
+}
+
+const void *verify_kernel_ptr(int layout) {
+    switch (layout) {
+        case L8x4x1: return reinterpret_cast<const void *>(&verify_kernel<8, 1>);
+        case L8x4x2: return reinterpret_cast<const void *>(&verify_kernel<8, 2>);
+        case L8x4x4: return reinterpret_cast<const void *>(&verify_kernel<8, 4>);
+        case L16x4x4: return reinterpret_cast<const void *>(&verify_kernel<16, 4>);
+        case L32x4x4: return reinterpret_cast<const void *>(&verify_kernel<32, 4>);
+        default: return reinterpret_cast<const void *>(&verify_kernel<64, 4>);
+    }
+}
+
+}  // namespace uhnsw

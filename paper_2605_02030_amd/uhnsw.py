@@ -1,0 +1,209 @@
+"""ctypes binding of libuhnsw (include/uhnsw.h): the same entry points, with
+argument marshalling only. Every step of the query path runs in the HIP
+kernels of libuhnsw.so; there is no CPU fallback. Importing this module on a
+tree without the built library raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libuhnsw.so")
+
+UHNSW_OK, UHNSW_EINVAL, UHNSW_ENOMEM, UHNSW_EDEVICE = 0, -1, -2, -3
+UHNSW_ESTATE, UHNSW_EIO, UHNSW_EBUSY, UHNSW_EUNSUPPORTED = -4, -5, -6, -7
+UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 1024, 1024
+STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
+UHNSW_QBAD, UHNSW_QCAP = 1, 2
+
+EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
+           "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
+                      "(or __graft_entry__.build()) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_I32, _I64 = ctypes.c_int32, ctypes.c_int64
+
+
+class uhnsw_graph(ctypes.Structure):
+    _fields_ = [("M", _I32), ("max_level", _I32), ("entry_point", _I32), ("level", _P),
+                ("n_nodes", _I64 * UHNSW_MAX_LAYERS), ("nodes", _P * UHNSW_MAX_LAYERS),
+                ("row_ptr", _P * UHNSW_MAX_LAYERS), ("col", _P * UHNSW_MAX_LAYERS)]
+
+
+class uhnsw_index(ctypes.Structure):
+    _fields_ = [("n", _I64), ("d", _I32), ("base", _P), ("storage", _I32), ("graphs", uhnsw_graph * 2)]
+
+
+class uhnsw_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("cutoff", ctypes.c_float), ("t", _I32), ("kappa", _I32),
+                ("beam_width", _I32), ("early_abort", _I32), ("visited_slots", _I32),
+                ("waves_per_block", _I32), ("persistent", _I32), ("timing", _I32)]
+
+
+STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end")
+STATS_DTYPE = np.dtype([(f, np.int32) for f in STATS_FIELDS[:8]] + [(f, np.uint32) for f in STATS_FIELDS[8:]])
+STATS_WORDS = len(STATS_FIELDS)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+uhnsw_default_params = _sig("uhnsw_default_params", None, [_P])
+uhnsw_create = _sig("uhnsw_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_P)])
+uhnsw_destroy = _sig("uhnsw_destroy", None, [_P])
+uhnsw_last_error = _sig("uhnsw_last_error", ctypes.c_char_p, [_P])
+uhnsw_load_graphs = _sig("uhnsw_load_graphs", ctypes.c_int, [_P, _P])
+uhnsw_search = _sig("uhnsw_search", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _I32, _P, _P, _P])
+uhnsw_search_device = _sig("uhnsw_search_device", ctypes.c_int,
+                           [_P, _P, _I64, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _I32, _P])
+uhnsw_get_layout = _sig("uhnsw_get_layout", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
+uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
+uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
+                         [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
+
+
+class UhnswError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"uhnsw error {code}: {msg}")
+        self.code = code
+
+
+def default_params(**kw) -> uhnsw_params:
+    p = uhnsw_params()
+    uhnsw_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _graph_struct(g, keep):
+    s = uhnsw_graph()
+    s.M = int(g.M)
+    s.max_level = int(g.max_level)
+    s.entry_point = int(g.entry)
+    lv = np.ascontiguousarray(g.levels, np.int8)
+    keep.append(lv)
+    s.level = lv.ctypes.data
+    for l, L in enumerate(g.layers):
+        rp = np.ascontiguousarray(L.row_ptr, np.int64)
+        col = np.ascontiguousarray(L.col, np.int32)
+        if col.size == 0:
+            col = np.zeros(1, np.int32)
+        keep += [rp, col]
+        s.row_ptr[l] = rp.ctypes.data
+        s.col[l] = col.ctypes.data
+        if l == 0:
+            s.n_nodes[l] = len(rp) - 1
+        else:
+            nodes = np.ascontiguousarray(L.nodes, np.int32)
+            keep.append(nodes)
+            s.nodes[l] = nodes.ctypes.data
+            s.n_nodes[l] = nodes.shape[0]
+    return s
+
+
+class Context:
+    """One libuhnsw context on one HIP device (owns the resident index)."""
+
+    def __init__(self, device: int = 0):
+        h = _P()
+        rc = uhnsw_create(device, ctypes.byref(h))
+        if rc != UHNSW_OK:
+            raise UhnswError(rc, uhnsw_last_error(None).decode())
+        self.h = h
+        self.n = self.d = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            uhnsw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != UHNSW_OK:
+            raise UhnswError(rc, uhnsw_last_error(self.h).decode())
+
+    def load_graphs(self, base, g1, g2, storage: int = STORE_F32) -> None:
+        """base: (n, d) FP32; g1 / g2: graphs with M, max_level, entry, levels,
+        layers[l].nodes / row_ptr / col (G1 under L1, G2 under L2)."""
+        base = np.ascontiguousarray(base, np.float32)
+        keep = [base]
+        idx = uhnsw_index()
+        idx.n, idx.d = base.shape
+        idx.base = base.ctypes.data
+        idx.storage = storage
+        idx.graphs[0] = _graph_struct(g1, keep)
+        idx.graphs[1] = _graph_struct(g2, keep)
+        self._check(uhnsw_load_graphs(self.h, ctypes.byref(idx)))
+        self.n, self.d = base.shape
+
+    def layout(self):
+        g, v = _I32(), _I32()
+        self._check(uhnsw_get_layout(self.h, ctypes.byref(g), ctypes.byref(v)))
+        return g.value, v.value
+
+    def search(self, queries, p, k, ef, params: uhnsw_params | None = None, k_stride: int | None = None):
+        """Host arrays in, host arrays out (synchronous)."""
+        queries = np.ascontiguousarray(queries, np.float32)
+        nq = queries.shape[0]
+        p = np.ascontiguousarray(p, np.float32)
+        k = np.ascontiguousarray(k, np.int32)
+        ef = np.ascontiguousarray(ef, np.int32)
+        ks = int(k_stride if k_stride is not None else (k.max() if nq else 1))
+        ids = np.empty((nq, ks), np.int64)
+        dists = np.empty((nq, ks), np.float32)
+        stats = np.zeros(nq, STATS_DTYPE)
+        prm = ctypes.byref(params) if params is not None else None
+        self._check(uhnsw_search(self.h, queries.ctypes.data, nq, p.ctypes.data, k.ctypes.data, ef.ctypes.data,
+                                 prm, ks, ids.ctypes.data, dists.ctypes.data, stats.ctypes.data))
+        return ids, dists, stats
+
+    def search_device(self, queries, p, k, ef, k_max: int, ef_max: int, ids, dists, stats=None,
+                      cand_ids=None, cand_keys=None, params: uhnsw_params | None = None, stream=None):
+        """torch device tensors in and out; asynchronous on ``stream`` (torch
+        stream or raw hipStream_t int; default: torch's current stream)."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        for t in (queries, p, k, ef, ids, dists):
+            assert t.is_cuda and t.is_contiguous()
+        assert queries.dtype == torch.float32 and p.dtype == torch.float32
+        assert k.dtype == torch.int32 and ef.dtype == torch.int32
+        assert ids.dtype == torch.int64 and dists.dtype == torch.float32
+        nq = queries.shape[0]
+        ks = ids.shape[1]
+        cs = cand_ids.shape[1] if cand_ids is not None else 0
+        prm = ctypes.byref(params) if params is not None else None
+        self._check(uhnsw_search_device(
+            self.h, queries.data_ptr(), nq, p.data_ptr(), k.data_ptr(), ef.data_ptr(), int(k_max), int(ef_max),
+            prm, ks, ids.data_ptr(), dists.data_ptr(), stats.data_ptr() if stats is not None else None,
+            cand_ids.data_ptr() if cand_ids is not None else None,
+            cand_keys.data_ptr() if cand_keys is not None else None, cs, stream))
+
+    def device_info(self):
+        cus, khz = _I32(), _I32()
+        self._check(uhnsw_device_info(self.h, ctypes.byref(cus), ctypes.byref(khz)))
+        return cus.value, khz.value
+
+    def last_timing(self):
+        w, v = ctypes.c_float(), ctypes.c_float()
+        self._check(uhnsw_last_timing(self.h, ctypes.byref(w), ctypes.byref(v)))
+        return w.value, v.value

@@ -43,7 +43,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.hb_build.restype = ctypes.c_void_p
         lib.hb_build.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
         lib.hb_max_level.restype = ctypes.c_int
         lib.hb_max_level.argtypes = [ctypes.c_void_p]
         lib.hb_entry.restype = ctypes.c_int32
@@ -133,7 +133,7 @@ def build_graph(base: np.ndarray, metric: int, M: int = 16, ef_construction: int
             return _load_file(path)
     lib = _load()
     t0 = time.time()
-    h = lib.hb_build(base.ctypes.data, n, d, metric, M, ef_construction, seed, threads)
+    h = lib.hb_build(base.ctypes.data, n, d, metric, M, ef_construction, seed, threads, int(verbose))
     if not h:
         raise ValueError("hnsw build rejected its arguments")
     try:

@@ -28,6 +28,7 @@
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -331,7 +332,8 @@ static uint64_t splitmix64(uint64_t x) {
 }
 
 /* ----------------------------------------------------------- public API */
-void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, uint64_t seed, int nthreads) {
+void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, uint64_t seed, int nthreads,
+               int verbose) {
     if (n < 1 || d < 1 || (metric != 1 && metric != 2) || M < 2 || M > 127 || efc < 1) return NULL;
     hb_t *g = (hb_t *)calloc(1, sizeof(hb_t));
     g->n = n;
@@ -423,6 +425,11 @@ void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, 
                 g->max_level = g->level[v];
                 g->entry = v;
             }
+        }
+        int64_t step = n / 10 > 0 ? n / 10 : 1;
+        if (verbose && (done / step) != ((done + b) / step)) {
+            fprintf(stderr, "[hnsw-build] L%d: %lld / %lld nodes\n", metric, (long long)(done + b), (long long)n);
+            fflush(stderr);
         }
         done += b;
     }

@@ -1,0 +1,61 @@
+"""CPU-side checks of the C-ABI library: it loads, it exports every entry
+point include/uhnsw.h declares, and the pure host helpers behave. No HIP
+device call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "uhnsw.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(uhnsw_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2605_02030_amd import uhnsw
+
+    return uhnsw
+
+
+def test_header_declares_north_star_entry_points():
+    names = _declared()
+    for must in ("uhnsw_load_graphs", "uhnsw_search", "uhnsw_search_device", "uhnsw_create", "uhnsw_destroy",
+                 "uhnsw_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in _declared():
+        assert hasattr(so, name), name
+    assert set(_declared()) == set(lib.EXPORTS)
+
+
+def test_default_params(lib):
+    p = lib.default_params()
+    assert abs(p.tau - 0.92) < 1e-15 and abs(p.cutoff - 1.4) < 1e-6
+    assert p.beam_width == 1 and p.early_abort == 1 and p.t == 0 and p.kappa == 0
+    q = lib.default_params(tau=0.5, beam_width=2)
+    assert q.tau == 0.5 and q.beam_width == 2
+
+
+def test_struct_sizes_match_header(lib):
+    # uhnsw_params: double + float + 8 int32 (+ padding to 8) = 48 bytes
+    assert ctypes.sizeof(lib.uhnsw_params) == 48
+    assert ctypes.sizeof(lib.uhnsw_graph) == 12 + 4 + 8 + 32 * 8 * 4  # M..entry, pad, level ptr, 4 arrays
+    assert lib.STATS_DTYPE.itemsize == 40
+
+
+def test_null_arguments_rejected_without_device(lib):
+    # these return before touching the HIP runtime
+    assert lib.uhnsw_create(0, None) == lib.UHNSW_EINVAL
+    assert lib.uhnsw_load_graphs(None, None) == lib.UHNSW_EINVAL
+    assert lib.uhnsw_search(None, None, 0, None, None, None, None, 0, None, None, None) == lib.UHNSW_EINVAL
+    lib.uhnsw_destroy(None)

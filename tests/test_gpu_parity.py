@@ -1,0 +1,263 @@
+"""GPU parity: the HIP query path (through the C-ABI) against the oracle, on
+the same seeded inputs. C must match bit for bit; top-K and N_p follow the
+near-tie rule of tests/parity.py; distances within 1e-5 of FP64."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import synth.graphs as sg  # noqa: E402
+from parity import check_row  # noqa: E402
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx1(torch_cuda, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    _say("load workload 1 graphs", wl.n, wl.d)
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g1, g2)
+    yield c
+    c.close()
+
+
+def run_device(torch, ctx, queries, p, k, ef, k_max, ef_max, params=None, c_stride=None):
+    from paper_2605_02030_amd import uhnsw
+
+    dev = torch.device("cuda:0")
+    nq = len(p)
+    cs = c_stride or ef_max
+    tq = torch.from_numpy(np.ascontiguousarray(queries, np.float32)).to(dev)
+    tp = torch.from_numpy(np.ascontiguousarray(p, np.float32)).to(dev)
+    tk = torch.from_numpy(np.ascontiguousarray(k, np.int32)).to(dev)
+    te = torch.from_numpy(np.ascontiguousarray(ef, np.int32)).to(dev)
+    ids = torch.empty((nq, k_max), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+    stats = torch.zeros((nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
+    cid = torch.empty((nq, cs), dtype=torch.int32, device=dev)
+    ckey = torch.empty((nq, cs), dtype=torch.float32, device=dev)
+    ctx.search_device(tq, tp, tk, te, k_max, ef_max, ids, dists, stats, cid, ckey, params=params)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(nq)
+    return ids.cpu().numpy(), dists.cpu().numpy(), st, cid.cpu().numpy(), ckey.cpu().numpy()
+
+
+def compare(base, G1, G2, D, queries, p, k, ef, gpu, g, v, w=1, tau=0.92, kappa_param=0, t_param=0,
+            max_excused=0.05):
+    ids, dists, st, cid, ckey = gpu
+    nq = len(p)
+    prm = oracle.Params(g=g, v=v, w=w, tau=tau, kappa=kappa_param, t_param=t_param)
+    cs = cid.shape[1]
+    o = oracle.query_batch(G1, G2, D, queries, p, k, ef, prm, k_stride=ids.shape[1], c_stride=cs)
+    ost = o["stats"]
+    # candidate generation: bit-exact
+    np.testing.assert_array_equal(st["graph"], ost["graph"])
+    np.testing.assert_array_equal(st["entry0"], ost["entry0"])
+    np.testing.assert_array_equal(st["nc"], ost["nc"])
+    np.testing.assert_array_equal(st["n_exp"], ost["n_exp"])
+    assert (st["n_b"] >= ost["n_b"]).all()
+    np.testing.assert_array_equal(cid, o["c_ids"])
+    np.testing.assert_array_equal(ckey, o["c_keys"])
+    assert (st["flags"] == 0).all()
+    # verification
+    n_exc = 0
+    for i in range(nq):
+        K = int(k[i])
+        kappa = kappa_param or max(K, 2)
+        m = oracle.m_of(tau, K)
+        r = check_row(base, queries[i], p[i], K, kappa, m, cid[i], ids[i], dists[i], int(st["n_p"][i]),
+                      o["ids"][i], int(ost["n_p"][i]))
+        n_exc += r == "excused"
+    assert n_exc <= max(1, max_excused * nq), f"{n_exc} of {nq} rows excused"
+    return n_exc
+
+
+def test_cfg1_parity(torch_cuda, ctx1, wl1):
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    _say("cfg1 parity, layout", g, v)
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    gpu = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64)
+    n_exc = compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v)
+    _say("excused rows", n_exc)
+
+
+@pytest.mark.parametrize("ef", [10, 16, 33, 128, 300])
+def test_cfg1_ef_sweep(torch_cuda, ctx1, wl1, ef):
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    nq = 37  # ragged against 4 waves per block
+    efa = np.full(nq, ef, np.int32)
+    k = np.full(nq, 10, np.int32)
+    gpu = run_device(torch_cuda, ctx1, wl.queries[:nq], wl.p[:nq], k, efa, 10, ef)
+    compare(wl.base, G1, G2, D, wl.queries[:nq], wl.p[:nq], k, efa, gpu, g, v)
+
+
+def test_cfg1_mixed_k_ef(torch_cuda, ctx1, wl1):
+    """Mixed K in {1, 10, 100} and ef in [K, 256] in one launch; special p values."""
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    rng = np.random.Generator(np.random.PCG64(21))
+    nq = wl.nq
+    k = np.array([1, 10, 100], np.int32)[np.arange(nq) % 3]
+    ef = np.array([rng.integers(kk, 257) for kk in k], np.int32)
+    p = wl.p.copy()
+    p[:8] = [0.5, 1.0, 1.5, 2.0, 1.4, 0.5, 2.0, 1.0]
+    gpu = run_device(torch_cuda, ctx1, wl.queries, p, k, ef, 100, 256)
+    compare(wl.base, G1, G2, D, wl.queries, p, k, ef, gpu, g, v)
+
+
+def test_cfg1_host_api_matches_device(torch_cuda, ctx1, wl1):
+    wl, _, _ = wl1
+    ids_h, d_h, st_h = ctx1.search(wl.queries, wl.p, wl.k, wl.ef)
+    ids_d, d_d, st_d, _, _ = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64)
+    np.testing.assert_array_equal(ids_h, ids_d)
+    np.testing.assert_array_equal(d_h, d_d)
+    for f in ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0"):
+        np.testing.assert_array_equal(st_h[f], st_d[f])
+
+
+@pytest.mark.parametrize("knobs", [dict(persistent=1), dict(waves_per_block=1), dict(visited_slots=64),
+                                   dict(visited_slots=8192, waves_per_block=1), dict(early_abort=0)])
+def test_schedule_invariance(torch_cuda, ctx1, wl1, knobs):
+    """Results do not depend on scheduling, block shape or visited-cache size."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    base = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64)
+    other = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64,
+                       params=uhnsw.default_params(**knobs))
+    for a, b in zip(base, other):
+        if a.dtype.names:
+            for f in a.dtype.names:
+                if f not in ("n_b", "t_begin", "t_end"):
+                    np.testing.assert_array_equal(a[f], b[f])
+        else:
+            np.testing.assert_array_equal(a, b)
+
+
+def test_beam_width_two(torch_cuda, ctx1, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    gpu = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64,
+                     params=uhnsw.default_params(beam_width=2))
+    compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, w=2)
+
+
+def test_tau_and_kappa_params(torch_cuda, ctx1, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    for tau, kappa, t in ((1.5, 0, 0), (0.5, 3, 0), (0.92, 7, 40)):
+        prm = uhnsw.default_params(tau=tau, kappa=kappa, t=t)
+        gpu = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64, params=prm)
+        compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, tau=tau, kappa_param=kappa,
+                t_param=t)
+
+
+def test_bad_queries_flagged(torch_cuda, ctx1, wl1):
+    """Device-side validation: bad rows are padded and flagged, the rest run."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    nq = 8
+    p = wl.p[:nq].copy()
+    k = np.full(nq, 10, np.int32)
+    ef = np.full(nq, 64, np.int32)
+    p[1] = np.nan
+    p[2] = 0.3
+    k[3] = 0
+    ef[4] = 5  # ef < k
+    ef[5] = 65  # above ef_max
+    q = wl.queries[:nq].copy()
+    q[6, 3] = np.nan
+    ids, dists, st, cid, _ = run_device(torch_cuda, ctx1, q, p, k, ef, 10, 64)
+    bad = [1, 2, 3, 4, 5, 6]
+    assert (st["flags"][bad] == uhnsw.UHNSW_QBAD).all()
+    assert (ids[bad] == -1).all() and np.isinf(dists[bad]).all() and (cid[bad] == -1).all()
+    good = [0, 7]
+    assert (st["flags"][good] == 0).all() and (ids[good] >= 0).all()
+
+
+def test_host_api_rejects(torch_cuda, ctx1, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    q = wl.queries[:2]
+    ok = dict(p=np.array([1.0, 1.0], np.float32), k=np.array([10, 10], np.int32), ef=np.array([64, 64], np.int32))
+    for field, val in (("p", [0.49, 1.0]), ("p", [np.nan, 1.0]), ("p", [2.01, 1.0]), ("k", [0, 10]),
+                       ("k", [257, 10]), ("ef", [9, 64]), ("ef", [1025, 64])):
+        args = dict(ok)
+        args[field] = np.array(val, args[field].dtype)
+        with pytest.raises(uhnsw.UhnswError) as e:
+            ctx1.search(q, **args)
+        assert e.value.code == uhnsw.UHNSW_EINVAL
+    with pytest.raises(uhnsw.UhnswError):
+        ctx1.search(q, k_stride=5, **ok)
+    qn = q.copy()
+    qn[1, 0] = np.inf
+    with pytest.raises(uhnsw.UhnswError):
+        ctx1.search(qn, **ok)
+    ids, d, st = ctx1.search(q[:0], ok["p"][:0], ok["k"][:0], ok["ef"][:0])
+    assert ids.shape[0] == 0
+
+
+def test_tiny_index_pads(torch_cuda):
+    """n = 3: |C| < K; rows are padded with -1 / +inf."""
+    from paper_2605_02030_amd import uhnsw
+
+    base = np.array([[0, 0], [1, 0], [0, 3]], np.float32)
+    g1 = sg.build_graph(base, 1, M=4, ef_construction=8, seed=1, cache=False)
+    g2 = sg.build_graph(base, 2, M=4, ef_construction=8, seed=1, cache=False)
+    c = uhnsw.Context(0)
+    c.load_graphs(base, g1, g2)
+    q = np.array([[0.1, 0.1], [0.9, 2.0]], np.float32)
+    ids, d, st = c.search(q, np.array([0.7, 1.9], np.float32), np.array([5, 5], np.int32),
+                          np.array([8, 8], np.int32))
+    c.close()
+    for i in range(2):
+        assert sorted(ids[i][:3].tolist()) == [0, 1, 2]
+        assert (ids[i][3:] == -1).all() and np.isinf(d[i][3:]).all()
+        dd = [oracle.lp_dist(base[j], q[i], [0.7, 1.9][i]) for j in ids[i][:3]]
+        np.testing.assert_allclose(d[i][:3], dd, rtol=1e-5)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_precision_forms_cfg1(torch_cuda, wl1, storage):
+    """BF16 / FP16 walk storage: C equals the oracle walking the same storage;
+    the re-rank reads FP32, so distances stay within 1e-5 of FP64."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g1, g2, storage=storage)
+    g, v = c.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base, storage=storage)
+    gpu = run_device(torch_cuda, c, wl.queries, wl.p, wl.k, wl.ef, 10, 64)
+    c.close()
+    compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v)
