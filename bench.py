@@ -29,6 +29,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the walk kernel from two rocprofv3 counter passes
+# (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0 per launch, valid only for that kernel source and ef.
+TRAFFIC = {"kernel_sha256_prefix": "3f5a50161a83efc2", "ef": 256, "bytes_per_launch": 30.276e9}
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
 TARGET_RECALL = 0.9
@@ -63,13 +68,25 @@ class Form:
         self.stats = torch.zeros((wl.nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
         self.ef_val = None
         self.ef = None
+        self.tuned = {}
 
     def set_ef(self, ef):
         self.ef_val = ef
         self.ef = self.torch.full((self.nq,), ef, dtype=torch_int32(self.torch), device="cuda:0")
+        if self.persistent and ef not in self.tuned:
+            base = self.uhnsw.default_params(fused=1, persistent=1, graph=1)
+            t = self.ctx.autotune(self.q, self.p, self.k, self.ef, 10, ef, params=base, allow_beam=True)
+            t.graph = 1
+            self.tuned[ef] = t
+            log(f"{self.name} ef={ef}: autotuned beam={t.beam_width} slots={t.visited_slots} "
+                f"wpb={t.waves_per_block} persistent={t.persistent}")
 
     def step(self, timing=False):
-        prm = self.uhnsw.default_params(persistent=self.persistent, timing=int(timing))
+        if self.persistent:  # batching form: fused persistent launch, autotuned, replayed as a hipGraph
+            prm = self.uhnsw.uhnsw_params.from_buffer_copy(self.tuned[self.ef_val])
+            prm.timing = int(timing)
+        else:
+            prm = self.uhnsw.default_params(timing=int(timing))
         self.ctx.search_device(self.q, self.p, self.k, self.ef, 10, self.ef_val, self.ids, self.dists, self.stats,
                                params=prm)
 
@@ -133,6 +150,40 @@ def timed(form, steps, warmup, wl, rate_khz):
                 n_p=float(st["n_p"].mean()), flags=int((st["flags"] != 0).sum()))
 
 
+def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000), seconds=0.5):
+    """Serving form: Poisson arrivals into the continuous-batching server."""
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16)
+    out = []
+    pos_of = {int(q): i for i, q in enumerate(gt["qidx"])}
+    for rate in rates:
+        n = min(wl.nq, int(rate * seconds))
+        rng = np.random.Generator(np.random.PCG64(rate))
+        arrival = np.cumsum(rng.exponential(1e6 / rate, n))
+        srv = uhnsw.Server(ctx, k_max=10, ef_max=ef,
+                           params=uhnsw.default_params(beam_width=2, visited_slots=1024))
+        try:
+            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[:n], wl.p[:n], wl.k[:n],
+                                                                    np.full(n, ef, np.int32), arrival)
+            info = srv.info()
+        finally:
+            srv.stop()
+        lat_ms = (t_done - t_sub) / 1e3
+        span_s = (t_done.max() - arrival[0]) / 1e6
+        sel = [i for i in range(n) if i in pos_of]
+        rec = float(np.mean([len(set(ids[i, :10].tolist()) & set(gt["ids"][pos_of[i]].tolist())) / 10
+                             for i in sel])) if sel else None
+        r = dict(offered_qps=rate, queries=n, achieved_qps=round(n / span_s, 1),
+                 p50_ms=round(float(np.percentile(lat_ms, 50)), 3), p99_ms=round(float(np.percentile(lat_ms, 99)), 3),
+                 recall_at_10=round(rec, 4) if rec is not None else None, batches=info["batches"],
+                 max_batches_in_flight=info["max_overlap"], errors=int((status != 0).sum()))
+        log("serving", json.dumps(r))
+        out.append(r)
+    ctx.close()
+    return dict(form="BF16 walk, beam 2, fused launches on 4 streams, continuous batching", ef=ef, k=10,
+                rates=out)
+
+
 def cpu_baseline(wl, g1, g2, ef, budget_s=15.0):
     """The oracle (plain C, OpenMP over queries) on a bounded query sample."""
     import oracle
@@ -160,6 +211,9 @@ def main():
     ap.add_argument("--ef", type=int, default=0, help="skip calibration, use this efSearch")
     ap.add_argument("--forms", default="fp32,bf16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the query path runs on a single MI355X and this build has no "
@@ -182,6 +236,15 @@ def main():
     t0 = time.time()
     g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
     log(f"graphs ready in {time.time() - t0:.1f}s")
+
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 1 GiB device copies done")
+        del src, dst
 
     forms = {}
     specs = {"fp32": (uhnsw.STORE_F32, 0, 4), "bf16-batched": (uhnsw.STORE_BF16, 1, 2)}
@@ -213,6 +276,10 @@ def main():
         del f
         torch.cuda.empty_cache()
 
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as fh:
+        kernel_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
     main_name = "fp32" if "fp32" in forms else next(iter(forms))
     m = forms[main_name]
     ef_main, r_main, ach_main = chosen_fp32 if chosen_fp32 else (m["ef"], None, m["walk_gbs"])
@@ -236,10 +303,14 @@ def main():
         "p50_ms": m["p50_ms"],
         "p99_ms": m["p99_ms"],
         "roofline": {"bound": "hbm", "achieved": round(ach_main, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach_main / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ach_main / HBM_PEAK_GBS, 4),
+                     "traffic": (TRAFFIC["bytes_per_launch"] if kernel_hash == TRAFFIC["kernel_sha256_prefix"]
+                                 and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" else None),
                      "kernel": "walk_kernel", "walk_ms": m["walk_ms"]},
         "forms": forms,
     }
+    if not a.no_serving:
+        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, forms[main_name]["ef"])
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl, g1, g2, m["ef"])

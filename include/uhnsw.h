@@ -91,8 +91,16 @@ typedef struct {
     int32_t early_abort;      /* exact partial-sum abort in verification      */
     int32_t visited_slots;    /* LDS visited-cache slots; 0 -> automatic      */
     int32_t waves_per_block;  /* 0 -> automatic                               */
-    int32_t persistent;       /* 1: one persistent launch with work stealing  */
+    int32_t persistent;       /* 1: persistent launch; waves take queries from
+                                 a work counter until none is left          */
     int32_t timing;           /* 1: record per-kernel times (uhnsw_last_timing)*/
+    int32_t fused;            /* 1: walk and verification in one kernel, C
+                                 kept in LDS (the batching form)             */
+    int32_t graph;            /* 1: capture the launch sequence as a hipGraph
+                                 on first use and replay it while the
+                                 arguments stay the same                     */
+    int32_t waves_per_cu;     /* persistent launch: resident waves per CU
+                                 (0 = as many as fit)                        */
 } uhnsw_params;
 
 /* Per-query counters (the N_b / N_p of the paper's cost model, Eq. 1). */
@@ -161,6 +169,21 @@ int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const 
                         int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
                         float *cand_keys, int32_t c_stride, void *stream);
 
+/* Batching form: pick execution knobs for this index and query mix by
+ * timing the search on the given device queries (same arrays and limits as
+ * uhnsw_search_device): visited-cache slots, waves per block, persistent or
+ * not, and -- only when allow_beam is set, since it changes the walk's
+ * trajectory -- the beam width. Every other knob leaves results unchanged.
+ * *prm is read for Algorithm 1's parameters and receives the chosen knobs.
+ * Results are cached per (n, d, storage, ef range, k_max) in the context. */
+int uhnsw_autotune(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t allow_beam, uhnsw_params *prm,
+                   void *stream);
+
+/* Number of hipGraph captures made so far (prm->graph); replays do not
+ * count. */
+int uhnsw_graph_captures(const uhnsw_ctx *ctx, int64_t *count);
+
 /* Lane layout of the walk's FP32 base distance for the loaded index:
  * element j is summed by lane (j / v) mod g, lanes combine pairwise. */
 int uhnsw_get_layout(const uhnsw_ctx *ctx, int32_t *g, int32_t *v);
@@ -172,6 +195,72 @@ int uhnsw_device_info(const uhnsw_ctx *ctx, int32_t *num_cus, int32_t *wall_cloc
 /* Kernel times (ms) of the last search run with prm->timing = 1, measured
  * with HIP events on the stream the kernels ran on. */
 int uhnsw_last_timing(const uhnsw_ctx *ctx, float *walk_ms, float *verify_ms);
+
+/* ------------------------------------------------------------ serving form
+ * Continuous batching over the loaded index. Queries are admitted into
+ * slots as they arrive; a dispatcher thread launches whatever is pending as
+ * one fused walk+verify launch on the first idle stream, so batches that
+ * arrive while others run overlap on the device. Admission: at most
+ * max_inflight queries at once (default: the device's resident-wave
+ * capacity, one wave per query, 16 per CU) and per-stream device buffers
+ * within hbm_budget. A query's result is the same whichever batch carries
+ * it. While a server runs, the context must not be used for other searches
+ * and must not be destroyed. */
+typedef struct uhnsw_server uhnsw_server;
+
+typedef struct {
+    int32_t k_max;            /* largest K a request may ask for (<= KMAX)   */
+    int32_t ef_max;           /* largest ef (<= EFMAX)                        */
+    int32_t max_inflight;     /* query slots, 0 = resident-wave capacity      */
+    int32_t max_batch;        /* queries per launch, 0 = capacity / streams   */
+    int32_t streams;          /* concurrent launches, 0 = 4 (<= 16)           */
+    int32_t reserved;
+    int64_t hbm_budget;       /* bytes for per-stream buffers, 0 = no limit  */
+    uhnsw_params params;      /* Algorithm 1 parameters; launches are fused   */
+} uhnsw_serve_config;
+
+typedef struct {
+    uint64_t tag;             /* the submitter's tag                          */
+    int32_t status;           /* UHNSW_OK, UHNSW_EINVAL (bad query), EDEVICE  */
+    int32_t nres;             /* valid entries in ids / dists                 */
+    double submit_us;         /* host clock (us since server start): admitted */
+    double launch_us;         /* its batch was launched                       */
+    double done_us;           /* its batch was seen complete                  */
+    uhnsw_stats stats;
+    int64_t ids[UHNSW_KMAX];  /* ascending (d_p, id); -1 padded               */
+    float dists[UHNSW_KMAX];  /* +inf padded                                  */
+} uhnsw_serve_result;
+
+void uhnsw_serve_default_config(uhnsw_serve_config *cfg);
+
+/* Start a server on a context with a loaded index.
+ * Errors: EINVAL (limits), ESTATE (no index), ENOMEM, EBUSY (hbm_budget
+ * below one query per stream). */
+int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out);
+
+/* Admit one query (copied; q has d floats). Thread-safe.
+ * Errors: EINVAL (p, k, ef out of range or q not finite), EBUSY (no free
+ * slot: retry after polling), ESTATE (stopping), or a sticky device error. */
+int uhnsw_serve_submit(uhnsw_server *srv, const float *q, float p, int32_t k, int32_t ef, uint64_t tag);
+
+/* Take up to max finished results (any order). Thread-safe. */
+int uhnsw_serve_poll(uhnsw_server *srv, uhnsw_serve_result *out, int32_t max, int32_t *n_out);
+
+/* Counters: info[0] slots, [1] free slots, [2] pending, [3] batches
+ * launched, [4] queries completed, [5] most batches in flight at once,
+ * [6] batch size limit, [7] streams. */
+int uhnsw_serve_info(uhnsw_server *srv, int64_t *info);
+
+/* Drive the server with a fixed arrival schedule (arrival_us[i] = offset of
+ * query i from the call, ascending): submit each at its time (waiting for
+ * slots when busy), collect every result into results[i]. Times in the
+ * results are in the caller's clock, submit_us = the scheduled arrival, so
+ * done_us - submit_us includes queueing. Synchronous. */
+int uhnsw_serve_drive(uhnsw_server *srv, int64_t n, const float *queries, const float *p, const int32_t *k,
+                      const int32_t *ef, const double *arrival_us, uhnsw_serve_result *results);
+
+/* Finish in-flight work, stop the dispatcher, free the server. */
+int uhnsw_serve_stop(uhnsw_server *srv);
 
 #ifdef __cplusplus
 }

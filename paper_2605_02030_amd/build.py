@@ -18,7 +18,7 @@ ARCH = os.environ.get("UHNSW_OFFLOAD_ARCH", "gfx950")
 DEVICE_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-ffp-contract=off",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-I", INCLUDE, "-I", CSRC]
-HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC]
+HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC]
 
 
 def build(verbose: bool = False) -> str:
@@ -27,7 +27,8 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     jobs = []
     for src, flags, lang in (("uhnsw_kernels.hip", DEVICE_FLAGS, ["-x", "hip"]),
-                             ("uhnsw_host.cpp", HOST_FLAGS, ["-D__HIP_PLATFORM_AMD__"])):
+                             ("uhnsw_host.cpp", HOST_FLAGS, ["-D__HIP_PLATFORM_AMD__"]),
+                             ("uhnsw_serve.cpp", HOST_FLAGS, ["-D__HIP_PLATFORM_AMD__", "-pthread"])):
         obj = os.path.join(bdir, src + ".o")
         cmd = ["hipcc", *lang, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
@@ -38,7 +39,7 @@ def build(verbose: bool = False) -> str:
         if j.wait() != 0:
             raise RuntimeError("hipcc failed")
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

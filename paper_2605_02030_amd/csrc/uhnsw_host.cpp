@@ -40,6 +40,13 @@ struct DevBuf {
     }
 };
 
+struct GraphKey {
+    const void *ptrs[9];
+    int64_t nq;
+    int32_t ints[4];
+    uhnsw_params prm;
+};
+
 struct GraphDev {
     DevBuf adj0, up_off, up_adj;
     int32_t entry = 0, max_level = 0, M = 0, M0 = 0;
@@ -68,7 +75,19 @@ struct uhnsw_ctx {
     // timing
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     bool timed = false;
+    // hipGraph of the last captured launch sequence
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    GraphKey gkey{};
+    int64_t graph_captures = 0;
+    // autotuner results keyed by (n, d, storage, ef bucket, k_max, beam, fused)
+    std::vector<std::pair<uint64_t, uhnsw_params>> tuned;
 };
+
+namespace uhnsw {
+int ctx_dim(const uhnsw_ctx *c) { return c->d; }
+int ctx_device(const uhnsw_ctx *c) { return c->device; }
+}  // namespace uhnsw
 
 namespace {
 
@@ -182,13 +201,13 @@ int upload_graph(uhnsw_ctx *c, const uhnsw_graph &g, int64_t n, GraphDev &gd) {
 }
 
 struct Plan {
-    int ef_cap, vis_bits, kv_cap, wpb, walk_bytes, verify_bytes;
+    int ef_cap, vis_bits, kv_cap, wpb, walk_bytes, verify_bytes, search_bytes;
 };
 
 int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan *pl) {
     pl->ef_cap = round_up(std::max(ef_max, 1), 4);
     int slots = prm.visited_slots;
-    if (slots <= 0) slots = ef_max <= 64 ? 2048 : ef_max <= 256 ? 4096 : 8192;
+    if (slots <= 0) slots = ef_max <= 256 ? 1024 : ef_max <= 512 ? 2048 : 4096;
     int bits = 0;
     while ((1 << bits) < slots) ++bits;
     if (bits < 6 || bits > 14) return fail(c, UHNSW_EINVAL, "visited_slots %d outside [64, 16384]", slots);
@@ -197,12 +216,14 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     pl->kv_cap = round_up(std::max(k_max, kappa_max), 4);
     pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits);
     pl->verify_bytes = verify_lds_bytes(pl->kv_cap);
-    const int per_wave = std::max(pl->walk_bytes, pl->verify_bytes);
+    // fused kernel: the verification's arrays follow the walk's list W
+    pl->search_bytes = std::max(pl->walk_bytes, pl->ef_cap * 8 + pl->verify_bytes);
+    const int per_wave = prm.fused ? pl->search_bytes : std::max(pl->walk_bytes, pl->verify_bytes);
     pl->wpb = prm.waves_per_block > 0 ? prm.waves_per_block : std::max(1, std::min(4, 65536 / per_wave));
     if (pl->wpb > 4) return fail(c, UHNSW_EINVAL, "waves_per_block %d > 4", pl->wpb);
-    if ((size_t)pl->walk_bytes * pl->wpb > 64 * 1024 || (size_t)pl->verify_bytes * pl->wpb > 64 * 1024)
-        return fail(c, UHNSW_EUNSUPPORTED, "LDS plan %d B/wave x %d waves exceeds 64 KiB per block",
-                    std::max(pl->walk_bytes, pl->verify_bytes), pl->wpb);
+    if ((size_t)per_wave * pl->wpb > 64 * 1024)
+        return fail(c, UHNSW_EUNSUPPORTED, "LDS plan %d B/wave x %d waves exceeds 64 KiB per block", per_wave,
+                    pl->wpb);
     return UHNSW_OK;
 }
 
@@ -294,6 +315,8 @@ void uhnsw_destroy(uhnsw_ctx *c) {
         g.up_off.reset();
         g.up_adj.reset();
     }
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -391,8 +414,8 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     if (ef_max < k_max || ef_max > UHNSW_EFMAX)
         return fail(c, UHNSW_EINVAL, "ef_max=%d outside [k_max, %d]", ef_max, UHNSW_EFMAX);
     if (k_stride < k_max) return fail(c, UHNSW_EINVAL, "k_stride=%d < k_max=%d", k_stride, k_max);
-    if ((cand_ids || cand_keys) && (!cand_ids || !cand_keys || c_stride < 1))
-        return fail(c, UHNSW_EINVAL, "candidate output needs both arrays and c_stride >= 1");
+    if ((cand_ids || cand_keys) && (!cand_ids || !cand_keys || c_stride < ef_max))
+        return fail(c, UHNSW_EINVAL, "candidate output needs both arrays and c_stride >= ef_max");
     uhnsw_params prm;
     if (prm_in)
         prm = *prm_in;
@@ -405,25 +428,6 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_OR_FAIL(c, hipSetDevice(c->device));
     if ((r = ensure_mtab(c, prm.tau))) return r;
-
-    // candidate lists: caller's buffers when given, else ours
-    const int32_t cs = cand_ids ? c_stride : ef_max;
-    int32_t *cid = cand_ids;
-    float *ckey = cand_keys;
-    if (!cid) {
-        HIP_OR_FAIL(c, c->cand_ids.ensure((size_t)nq * cs * 4));
-        HIP_OR_FAIL(c, c->cand_keys.ensure((size_t)nq * cs * 4));
-        cid = c->cand_ids.as<int32_t>();
-        ckey = c->cand_keys.as<float>();
-    } else if (c_stride < ef_max) {
-        return fail(c, UHNSW_EINVAL, "c_stride=%d < ef_max=%d", c_stride, ef_max);
-    }
-    HIP_OR_FAIL(c, c->ncand.ensure((size_t)nq * 4));
-    uhnsw_stats *st = stats;
-    if (!st) {
-        HIP_OR_FAIL(c, c->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
-        st = c->stats.as<uhnsw_stats>();
-    }
 
     SearchArgs a{};
     a.walk_base = c->storage == UHNSW_STORE_F32 ? c->f32_base.p : c->walk_base.p;
@@ -458,36 +462,203 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     a.vis_bits = pl.vis_bits;
     a.kv_cap = pl.kv_cap;
     a.waves_per_block = pl.wpb;
-    a.cand_ids = cid;
-    a.cand_keys = ckey;
-    a.c_stride = cs;
-    a.ncand = c->ncand.as<int32_t>();
     a.ids = ids;
     a.dists = dists;
     a.k_stride = k_stride;
-    a.stats = st;
     a.counter = nullptr;
-
-    const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
-    int walk_grid = grid_all;
-    if (prm.persistent) {
-        HIP_OR_FAIL(c, c->counter.ensure(4));
-        a.counter = c->counter.as<int32_t>();
-        int per_cu = 0;
-        HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, walk_kernel_ptr(c->layout), pl.wpb * kWave,
-                                                                    (size_t)pl.walk_bytes * pl.wpb));
-        walk_grid = std::max(1, std::min(grid_all, per_cu * c->num_cus));
-        HIP_OR_FAIL(c, launch_fill_i32(a.counter, 0, 1, s));
+    a.order = nullptr;
+    if (stats) {
+        a.stats = stats;
+    } else {
+        HIP_OR_FAIL(c, c->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
+        a.stats = c->stats.as<uhnsw_stats>();
     }
+    if (prm.fused) {
+        a.cand_ids = cand_ids;  // C stays in LDS unless the caller asks for it
+        a.cand_keys = cand_keys;
+        a.c_stride = cand_ids ? c_stride : 0;
+        a.ncand = nullptr;
+    } else {
+        const int32_t cs = cand_ids ? c_stride : ef_max;
+        if (!cand_ids) {
+            HIP_OR_FAIL(c, c->cand_ids.ensure((size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, c->cand_keys.ensure((size_t)nq * cs * 4));
+        }
+        HIP_OR_FAIL(c, c->ncand.ensure((size_t)nq * 4));
+        a.cand_ids = cand_ids ? cand_ids : c->cand_ids.as<int32_t>();
+        a.cand_keys = cand_ids ? cand_keys : c->cand_keys.as<float>();
+        a.c_stride = cs;
+        a.ncand = c->ncand.as<int32_t>();
+    }
+    if (prm.persistent) HIP_OR_FAIL(c, c->counter.ensure(4));
+
+    // the kernels of one search, in stream order
+    const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
+    int pgrid = grid_all;
+    if (prm.persistent) {
+        int per_cu = 0;
+        const void *kp =
+            prm.fused ? search_kernel_ptr(c->layout, c->storage) : walk_kernel_ptr(c->layout, c->storage);
+        const size_t lds_block = (size_t)(prm.fused ? pl.search_bytes : pl.walk_bytes) * pl.wpb;
+        HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, pl.wpb * kWave, lds_block));
+        per_cu = std::max(per_cu, 1);
+        if (prm.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, prm.waves_per_cu / pl.wpb));
+        pgrid = std::max(1, std::min(grid_all, per_cu * c->num_cus));
+    }
+    auto enqueue = [&](hipStream_t st, bool timed) -> hipError_t {
+        hipError_t e = hipSuccess;
+        SearchArgs b = a;
+        if (prm.persistent) {
+            b.counter = c->counter.as<int32_t>();
+            if ((e = launch_fill_i32(b.counter, 0, 1, st)) != hipSuccess) return e;
+        }
+        if (timed && (e = hipEventRecord(c->ev[0], st)) != hipSuccess) return e;
+        if (prm.fused) {
+            b.lds_wave_bytes = pl.search_bytes;
+            if ((e = launch_search(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
+            if (timed && (e = hipEventRecord(c->ev[1], st)) != hipSuccess) return e;
+        } else {
+            b.lds_wave_bytes = pl.walk_bytes;
+            if ((e = launch_walk(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
+            if (timed && (e = hipEventRecord(c->ev[1], st)) != hipSuccess) return e;
+            b.lds_wave_bytes = pl.verify_bytes;
+            b.counter = nullptr;
+            if ((e = launch_verify(b, c->layout, grid_all, st)) != hipSuccess) return e;
+        }
+        if (timed && (e = hipEventRecord(c->ev[2], st)) != hipSuccess) return e;
+        return hipSuccess;
+    };
+
     c->timed = prm.timing != 0;
+    if (!prm.graph) {
+        HIP_OR_FAIL(c, enqueue(s, c->timed));
+        return UHNSW_OK;
+    }
+    // hipGraph: capture the launch sequence once per distinct argument set,
+    // replay it afterwards (kernel arguments are baked into the graph)
+    GraphKey key{};
+    key.ptrs[0] = queries;
+    key.ptrs[1] = p;
+    key.ptrs[2] = k;
+    key.ptrs[3] = ef;
+    key.ptrs[4] = ids;
+    key.ptrs[5] = dists;
+    key.ptrs[6] = stats;
+    key.ptrs[7] = cand_ids;
+    key.ptrs[8] = cand_keys;
+    key.nq = nq;
+    key.ints[0] = k_max;
+    key.ints[1] = ef_max;
+    key.ints[2] = k_stride;
+    key.ints[3] = c_stride;
+    key.prm = prm;
+    key.prm.timing = 0;
+    key.prm.graph = 0;
+    if (!c->gexec || std::memcmp(&key, &c->gkey, sizeof key) != 0) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        if (!c->cap_stream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_OR_FAIL(c, hipStreamSynchronize(s));
+        HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue(c->cap_stream, false);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (e != hipSuccess) return dev_fail(c, e, "enqueue under capture");
+        if (e2 != hipSuccess) return dev_fail(c, e2, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate");
+        c->gkey = key;
+        ++c->graph_captures;
+    }
     if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], s));
-    a.lds_wave_bytes = pl.walk_bytes;
-    HIP_OR_FAIL(c, launch_walk(a, c->layout, walk_grid, s));
-    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[1], s));
-    a.lds_wave_bytes = pl.verify_bytes;
-    a.counter = nullptr;
-    HIP_OR_FAIL(c, launch_verify(a, c->layout, grid_all, s));
-    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[2], s));
+    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, s));
+    if (c->timed) {
+        HIP_OR_FAIL(c, hipEventRecord(c->ev[1], s));
+        HIP_OR_FAIL(c, hipEventRecord(c->ev[2], s));
+    }
+    return UHNSW_OK;
+}
+
+int uhnsw_graph_captures(const uhnsw_ctx *c, int64_t *count) {
+    if (!c || !count) return UHNSW_EINVAL;
+    *count = c->graph_captures;
+    return UHNSW_OK;
+}
+
+int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t allow_beam, uhnsw_params *prm,
+                   void *stream) {
+    if (!c || !prm) return UHNSW_EINVAL;
+    if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
+    if (nq < 1) return fail(c, UHNSW_EINVAL, "autotune needs queries");
+    const uint64_t key = ((uint64_t)c->n << 20) ^ ((uint64_t)c->d << 8) ^ ((uint64_t)c->storage << 4) ^
+                         ((uint64_t)(ef_max <= 64 ? 0 : ef_max <= 128 ? 1 : ef_max <= 256 ? 2 : 3) << 40) ^
+                         ((uint64_t)k_max << 44) ^ ((uint64_t)(allow_beam != 0) << 60) ^
+                         ((uint64_t)(prm->fused != 0) << 61);
+    for (auto &e : c->tuned)
+        if (e.first == key) {
+            uhnsw_params t = e.second;
+            t.tau = prm->tau;
+            t.cutoff = prm->cutoff;
+            t.t = prm->t;
+            t.kappa = prm->kappa;
+            t.early_abort = prm->early_abort;
+            t.timing = prm->timing;
+            t.graph = prm->graph;
+            *prm = t;
+            return UHNSW_OK;
+        }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    DevBuf oid, od, os;
+    HIP_OR_FAIL(c, oid.ensure((size_t)nq * k_max * 8));
+    HIP_OR_FAIL(c, od.ensure((size_t)nq * k_max * 4));
+    HIP_OR_FAIL(c, os.ensure((size_t)nq * sizeof(uhnsw_stats)));
+    uhnsw_params best = *prm;
+    float best_ms = 1e30f;
+    const int slots_c[] = {512, 1024, 2048, 4096};
+    const int wpb_c[] = {1, 2, 4};
+    for (int beam = 1; beam <= (allow_beam ? 2 : 1); ++beam)
+        for (int sl : slots_c)
+            for (int wpb : wpb_c)
+                for (int pers = 0; pers <= 1; ++pers) {
+                    uhnsw_params t = *prm;
+                    t.beam_width = beam;
+                    t.visited_slots = sl;
+                    t.waves_per_block = wpb;
+                    t.persistent = pers;
+                    t.waves_per_cu = 0;
+                    t.graph = 0;
+                    t.timing = 1;
+                    float ms[3];
+                    bool ok = true;
+                    for (int rep = -1; rep < 3 && ok; ++rep) {
+                        int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
+                                                     oid.as<int64_t>(), od.as<float>(), os.as<uhnsw_stats>(),
+                                                     nullptr, nullptr, 0, s);
+                        if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
+                            ok = false;  // this shape does not fit: skip it
+                            c->err.clear();
+                            break;
+                        }
+                        if (rc) return rc;
+                        float w = 0, v = 0;
+                        if ((rc = uhnsw_last_timing(c, &w, &v))) return rc;
+                        if (rep >= 0) ms[rep] = w + v;
+                    }
+                    if (!ok) continue;
+                    std::sort(ms, ms + 3);
+                    if (ms[1] < best_ms) {
+                        best_ms = ms[1];
+                        best = t;
+                    }
+                }
+    best.timing = prm->timing;
+    best.graph = prm->graph;
+    c->tuned.emplace_back(key, best);
+    *prm = best;
     return UHNSW_OK;
 }
 

@@ -71,16 +71,21 @@ struct SearchArgs {
     uhnsw_stats *stats;
     // persistent scheduling
     int32_t *counter;       // nullptr: one wave per query by grid position
+    const int32_t *order;   // persistent order of queries (nullptr: 0..nq-1)
 };
 
 // Launchers (uhnsw_kernels.hip). Return the HIP status of the launch.
 hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s);
+hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
 int walk_lds_bytes(int ef_cap, int vis_bits);
 int verify_lds_bytes(int kv_cap);
-const void *walk_kernel_ptr(int layout);
+const void *walk_kernel_ptr(int layout, int storage);
 const void *verify_kernel_ptr(int layout);
+const void *search_kernel_ptr(int layout, int storage);
+int ctx_dim(const uhnsw_ctx *c);
+int ctx_device(const uhnsw_ctx *c);
 
 }  // namespace uhnsw

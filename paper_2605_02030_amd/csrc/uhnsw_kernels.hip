@@ -66,17 +66,23 @@ __device__ __forceinline__ void wave_argmin(float &k, int32_t &id) {
 }
 
 // ------------------------------------------------------- element loading
+// Four consecutive elements per lane load. Loads land in `Raw` registers
+// (packed 16-bit pairs for BF16 / FP16, so a row in flight costs half the
+// VGPRs) and are widened exactly to FP32 only when used.
 template <typename T>
 struct Elem;
 template <>
 struct Elem<float> {
-    __device__ static __forceinline__ void load4(const float *p, float (&x)[4]) {
-        float4 v = *reinterpret_cast<const float4 *>(p);
+    using Raw = float4;
+    __device__ static __forceinline__ Raw load(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+    __device__ static __forceinline__ Raw zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static __forceinline__ void widen(const Raw &v, float (&x)[4]) {
         x[0] = v.x;
         x[1] = v.y;
         x[2] = v.z;
         x[3] = v.w;
     }
+    __device__ static __forceinline__ void load4(const float *p, float (&x)[4]) { widen(load(p), x); }
 };
 struct bf16_t {
     uint16_t b;
@@ -86,8 +92,10 @@ struct f16_t {
 };
 template <>
 struct Elem<bf16_t> {
-    __device__ static __forceinline__ void load4(const bf16_t *p, float (&x)[4]) {
-        uint2 v = *reinterpret_cast<const uint2 *>(p);
+    using Raw = uint2;
+    __device__ static __forceinline__ Raw load(const bf16_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+    __device__ static __forceinline__ Raw zero() { return make_uint2(0u, 0u); }
+    __device__ static __forceinline__ void widen(const Raw &v, float (&x)[4]) {
         x[0] = __uint_as_float(v.x << 16);
         x[1] = __uint_as_float(v.x & 0xffff0000u);
         x[2] = __uint_as_float(v.y << 16);
@@ -96,8 +104,10 @@ struct Elem<bf16_t> {
 };
 template <>
 struct Elem<f16_t> {
-    __device__ static __forceinline__ void load4(const f16_t *p, float (&x)[4]) {
-        uint2 v = *reinterpret_cast<const uint2 *>(p);
+    using Raw = uint2;
+    __device__ static __forceinline__ Raw load(const f16_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+    __device__ static __forceinline__ Raw zero() { return make_uint2(0u, 0u); }
+    __device__ static __forceinline__ void widen(const Raw &v, float (&x)[4]) {
         x[0] = __half2float(__ushort_as_half((unsigned short)(v.x & 0xffffu)));
         x[1] = __half2float(__ushort_as_half((unsigned short)(v.x >> 16)));
         x[2] = __half2float(__ushort_as_half((unsigned short)(v.y & 0xffffu)));
@@ -116,37 +126,39 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
     constexpr int RB = (64 / (NCH * V)) > 0 ? (64 / (NCH * V)) : 1;
+    using E = Elem<T>;
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
     for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
-        float x[RB][NCH][V];
+        typename E::Raw raw[RB][NCH];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             const int row = r0 + b * RPW + grp;
             if (row < nrows) {
                 const T *rp = base + (int64_t)ids[row] * pitch + gl * V;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) Elem<T>::load4(rp + c * G * V, x[b][c]);
+                for (int c = 0; c < NCH; ++c) raw[b][c] = E::load(rp + c * G * V);
             } else {
 #pragma unroll
-                for (int c = 0; c < NCH; ++c)
-#pragma unroll
-                    for (int e = 0; e < V; ++e) x[b][c][e] = 0.0f;
+                for (int c = 0; c < NCH; ++c) raw[b][c] = E::zero();
             }
         }
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             float s = 0.0f;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
+            for (int c = 0; c < NCH; ++c) {
+                float x[V];
+                E::widen(raw[b][c], x);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
-                    const float dlt = x[b][c][e] - qv[c][e];
+                    const float dlt = x[e] - qv[c][e];
                     if (L1)
                         s = s + fabsf(dlt);
                     else
                         s = __builtin_fmaf(dlt, dlt, s);
                 }
+            }
             s = group_sum<G>(s);
             const int row = r0 + b * RPW + grp;
             if (row < nrows && gl == 0) keys[row] = s;
@@ -315,7 +327,7 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
 }
 
 template <int G, int NCH, typename T>
-__device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
+__device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
     const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits);
@@ -323,25 +335,26 @@ __device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int K = A.k[qi];
     const int ef = A.ef[qi];
     uhnsw_stats *st = A.stats + qi;
-    int32_t *cid = A.cand_ids + qi * A.c_stride;
-    float *ckey = A.cand_keys + qi * A.c_stride;
+    int32_t *cid = A.cand_ids ? A.cand_ids + qi * A.c_stride : nullptr;
+    float *ckey = A.cand_keys ? A.cand_keys + qi * A.c_stride : nullptr;
     bool finite = true;
     for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
     const bool bad = query_bad(A, p, K, ef) || ballot(!finite) != 0;
     if (bad) {
-        for (int i = lane; i < A.c_stride; i += kWave) {
-            cid[i] = -1;
-            ckey[i] = INFINITY;
-        }
+        if (cid)
+            for (int i = lane; i < A.c_stride; i += kWave) {
+                cid[i] = -1;
+                ckey[i] = INFINITY;
+            }
         if (lane == 0) {
-            A.ncand[qi] = -1;
+            if (A.ncand) A.ncand[qi] = -1;
             st->graph = 0;
             st->n_b = st->n_exp = st->n_p = st->batches = st->nc = 0;
             st->flags = UHNSW_QBAD;
             st->entry0 = -1;
             st->t_begin = st->t_end = t_begin;
         }
-        return;
+        return -1;
     }
     const int gsel = (p <= A.cutoff) ? 0 : 1;
     const DevGraph &Gr = A.g[gsel];
@@ -409,30 +422,35 @@ __device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     }
     wave_sync();
     int nW = 1, lb = 0, n_exp = 0, flags = 0;
+    int32_t spec_node = -1, spec_nb = -1;  // prefetched adjacency row (beam 1)
     const int M0 = Gr.M0;
     const int beam = A.beam;
     for (;;) {
         // the first `beam` (1 or 2) unexpanded entries, scanning from lb;
-        // all values here are wave-uniform (LDS broadcast reads)
-        int npick = 0, pos0 = -1, pos1 = -1;
+        // all values here are wave-uniform (LDS broadcast reads). With beam 1
+        // the second unexpanded entry is found too: its adjacency row is
+        // fetched early, and used if it turns out to be the next pick.
+        int npick = 0, pos0 = -1, pos1 = -1, nseen = 0;
         uint32_t node0 = 0, node1 = 0;
-        for (int b0 = lb; b0 < nW && npick < beam; b0 += kWave) {
+        const int want = beam == 1 ? 2 : beam;
+        for (int b0 = lb; b0 < nW && nseen < want; b0 += kWave) {
             const int i = b0 + lane;
             const bool un = i < nW && !(L.Wi[i] & kExpBit);
             uint64_t m = ballot(un);
-            while (m && npick < beam) {
+            while (m && nseen < want) {
                 const int pos = b0 + __ffsll((unsigned long long)m) - 1;
                 m &= m - 1;
-                if (npick == 0) {
+                if (nseen == 0) {
                     pos0 = pos;
                     node0 = L.Wi[pos];
                 } else {
                     pos1 = pos;
                     node1 = L.Wi[pos];
                 }
-                ++npick;
+                ++nseen;
             }
         }
+        npick = beam == 1 ? (nseen > 0 ? 1 : 0) : nseen;
         if (npick == 0) break;
         if (n_exp >= A.n) {  // a valid walk expands each node at most once
             flags |= UHNSW_QCAP;
@@ -448,7 +466,16 @@ __device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         // neighbours: lane = slot `lane % M0` of picked node `lane / M0`
         const int which = lane / M0, slot = lane % M0;
         int32_t nb = -1;
-        if (which < npick) nb = Gr.adj0[(int64_t)(which == 0 ? node0 : node1) * M0 + slot];
+        if (beam == 1) {
+            if ((int32_t)node0 == spec_node)
+                nb = spec_nb;
+            else if (which == 0)
+                nb = Gr.adj0[(int64_t)node0 * M0 + slot];
+            spec_node = nseen > 1 ? (int32_t)node1 : -1;
+            if (nseen > 1 && which == 0) spec_nb = Gr.adj0[(int64_t)node1 * M0 + slot];
+        } else if (which < npick) {
+            nb = Gr.adj0[(int64_t)(which == 0 ? node0 : node1) * M0 + slot];
+        }
         bool fresh = false;
         uint32_t vs = 0;
         if (nb >= 0) {
@@ -473,12 +500,13 @@ __device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
 
     // ---- C = first t of W
     const int nc = nW < t ? nW : t;
-    for (int i = lane; i < A.c_stride; i += kWave) {
-        cid[i] = i < nc ? (int32_t)(L.Wi[i] & kIdMask) : -1;
-        ckey[i] = i < nc ? L.Wk[i] : INFINITY;
-    }
+    if (cid)
+        for (int i = lane; i < A.c_stride; i += kWave) {
+            cid[i] = i < nc ? (int32_t)(L.Wi[i] & kIdMask) : -1;
+            ckey[i] = i < nc ? L.Wk[i] : INFINITY;
+        }
     if (lane == 0) {
-        A.ncand[qi] = nc;
+        if (A.ncand) A.ncand[qi] = nc;
         st->graph = gsel + 1;
         st->n_b = n_b;
         st->n_exp = n_exp;
@@ -487,6 +515,7 @@ __device__ void walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         st->entry0 = entry0;
         st->t_begin = t_begin;
     }
+    return nc;
 }
 
 // Next query index for this wave from the work counter. Every lane issues
@@ -497,13 +526,11 @@ __device__ __forceinline__ int fetch_query(int32_t *counter) {
     return __builtin_amdgcn_readfirstlane(__shfl(v, 0, kWave));
 }
 
+// 4 waves per SIMD: with a 1,024-slot visited cache LDS admits 16+ waves per
+// CU, and the extra resident waves hide more gather latency than the few
+// spilled registers cost.
 template <int G, int NCH, typename T>
-__device__ __noinline__ void walk_query(const SearchArgs &A, int64_t qi, char *lds) {
-    walk_one<G, NCH, T>(A, qi, lds);
-}
-
-template <int G, int NCH, typename T>
-__global__ void __launch_bounds__(256) walk_kernel(SearchArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) walk_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
@@ -515,7 +542,7 @@ __global__ void __launch_bounds__(256) walk_kernel(SearchArgs A) {
     // persistent: waves take queries from the counter until it passes nq
     int qi = fetch_query(A.counter);
     while ((int64_t)qi < A.nq) {
-        walk_query<G, NCH, T>(A, qi, lds);
+        walk_one<G, NCH, T>(A, qi, lds);
         qi = fetch_query(A.counter);
     }
 }
@@ -542,7 +569,8 @@ __device__ __forceinline__ void rows_lp(const float *__restrict__ base, int64_t 
                                         float *S) {
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
-    constexpr int RB = (64 / (NCH * V)) > 0 ? (64 / (NCH * V)) : 1;
+    // verification batches are small (kappa rows): two row-steps in flight
+    constexpr int RB = (32 / (NCH * V)) > 0 ? (32 / (NCH * V)) : 1;
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
     for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
@@ -617,8 +645,11 @@ __device__ inline VerifyLds verify_lds(char *p, int kv_cap) {
     return L;
 }
 
+// Verification of one query. C comes from global memory (Cg) or, in the
+// fused kernel, straight from the walk's list in LDS (Cl, expanded bit set).
 template <int G, int NCH>
-__device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
+__device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, const int32_t *Cg,
+                           const uint32_t *Cl) {
     const int lane = lane_id();
     const float p = A.p[qi];
     const int K = A.k[qi];
@@ -626,7 +657,6 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
     int64_t *oid = A.ids + qi * A.k_stride;
     float *odist = A.dists + qi * A.k_stride;
     uhnsw_stats *st = A.stats + qi;
-    const int nc = A.ncand[qi];
     if (nc < 0) {  // rejected by the walk
         for (int r = lane; r < A.k_stride; r += kWave) {
             oid[r] = -1;
@@ -639,7 +669,6 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
     const VerifyLds L = verify_lds(lds, A.kv_cap);
     const int pc = p == 1.0f ? 1 : p == 2.0f ? 2 : p == 0.5f ? 3 : p == 1.5f ? 4 : 0;
     const int m = A.mtab[K];
-    const int32_t *C = A.cand_ids + qi * A.c_stride;
     float qv[NCH][4];
     {
         const int gl = lane % G;
@@ -654,7 +683,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
     }
     // R = first K of C
     const int nR = nc < K ? nc : K;
-    for (int i = lane; i < nR; i += kWave) L.Bi[i] = C[i];
+    for (int i = lane; i < nR; i += kWave) L.Bi[i] = Cl ? (int32_t)(Cl[i] & kIdMask) : Cg[i];
     wave_sync();
     lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nR, qv, p, 0.0f, false, L.Bk);
     wave_sync();
@@ -666,7 +695,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds) {
         const int nb = nc - pos < kappa ? nc - pos : kappa;
         const float thr = L.Rk[nr - 1];
         wave_sync();
-        for (int i = lane; i < nb; i += kWave) L.Bi[i] = C[pos + i];
+        for (int i = lane; i < nb; i += kWave) L.Bi[i] = Cl ? (int32_t)(Cl[pos + i] & kIdMask) : Cg[pos + i];
         wave_sync();
         lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nb, qv, p, thr, A.early_abort != 0, L.Bk);
         wave_sync();
@@ -700,7 +729,50 @@ __global__ void __launch_bounds__(256) verify_kernel(SearchArgs A) {
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
-    if (qi < A.nq) verify_one<G, NCH>(A, qi, lds);
+    if (qi < A.nq) verify_one<G, NCH>(A, qi, lds, A.ncand[qi], A.cand_ids + qi * A.c_stride, nullptr);
+}
+
+// Fused walk + verification, one wave per query; with a work counter the
+// launch is persistent and waves keep taking queries (in `order` when given)
+// until the counter passes nq. C stays in LDS between the two phases; the
+// verification's arrays reuse the visited-cache region.
+template <int G, int NCH>
+__device__ __forceinline__ void verify_call(const SearchArgs &A, int64_t qi, char *lds, int nc,
+                                            const uint32_t *Cl) {
+    verify_one<G, NCH>(A, qi, lds, nc, nullptr, Cl);
+}
+
+// Occupancy target of the fused kernel: 3 waves per SIMD (<= 168 VGPRs) with
+// FP32 rows in flight, 4 (<= 128) with packed 16-bit rows.
+template <typename T>
+constexpr int fused_waves_per_eu() { return sizeof(T) == 4 ? 3 : 4; }
+
+template <int G, int NCH, typename T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T>(), 8)))
+search_kernel(SearchArgs A) {
+    extern __shared__ char lds_all[];
+    const int wave = threadIdx.x / kWave;
+    char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
+    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits);
+    char *vlds = lds + (size_t)A.ef_cap * 8;
+    if (A.counter == nullptr) {
+        const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
+        if (qi < A.nq) {
+            const int nc = walk_one<G, NCH, T>(A, qi, lds);
+            wave_sync();
+            verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
+        }
+        return;
+    }
+    int k = fetch_query(A.counter);
+    while ((int64_t)k < A.nq) {
+        const int64_t qi = A.order ? A.order[k] : k;
+        const int nc = walk_one<G, NCH, T>(A, qi, lds);
+        wave_sync();
+        verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
+        wave_sync();
+        k = fetch_query(A.counter);
+    }
 }
 
 // ------------------------------------------------------------- utilities
@@ -763,6 +835,21 @@ hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s) {
+    const dim3 blk(a.waves_per_block * kWave);
+    const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
+#define S_LAUNCH(G, NCH)                                                                          \
+    if (a.storage == UHNSW_STORE_F32)                                                             \
+        hipLaunchKernelGGL((search_kernel<G, NCH, float>), dim3(grid), blk, lds, s, a);           \
+    else if (a.storage == UHNSW_STORE_BF16)                                                       \
+        hipLaunchKernelGGL((search_kernel<G, NCH, bf16_t>), dim3(grid), blk, lds, s, a);          \
+    else                                                                                          \
+        hipLaunchKernelGGL((search_kernel<G, NCH, f16_t>), dim3(grid), blk, lds, s, a);
+    UHNSW_LAYOUT_SWITCH(layout, S_LAUNCH)
+#undef S_LAUNCH
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
@@ -781,16 +868,26 @@ hipError_t launch_convert(const float *src, void *dst, int64_t count, int storag
 int walk_lds_bytes(int ef_cap, int vis_bits) { return walk_lds_bytes_impl(ef_cap, vis_bits); }
 int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
 
-const void *walk_kernel_ptr(int layout) {
-    switch (layout) {
-        case L8x4x1: return reinterpret_cast<const void *>(&walk_kernel<8, 1, float>);
-        case L8x4x2: return reinterpret_cast<const void *>(&walk_kernel<8, 2, float>);
-        case L8x4x4: return reinterpret_cast<const void *>(&walk_kernel<8, 4, float>);
-        case L16x4x4: return reinterpret_cast<const void *>(&walk_kernel<16, 4, float>);
-        case L32x4x4: return reinterpret_cast<const void *>(&walk_kernel<32, 4, float>);
-        default: return reinterpret_cast<const void *>(&walk_kernel<64, 4, float>);
+// Host stubs of the kernels, by row layout and storage (for occupancy queries).
+#define UHNSW_STUB(NAME, G, NCH, storage)                                            \
+    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&NAME<G, NCH, float>)  \
+     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&NAME<G, NCH, bf16_t>) \
+                                   : reinterpret_cast<const void *>(&NAME<G, NCH, f16_t>))
+#define UHNSW_STUBS(NAME)                                                  \
+    const void *NAME##_ptr(int layout, int storage) {                      \
+        switch (layout) {                                                  \
+            case L8x4x1: return UHNSW_STUB(NAME, 8, 1, storage);           \
+            case L8x4x2: return UHNSW_STUB(NAME, 8, 2, storage);           \
+            case L8x4x4: return UHNSW_STUB(NAME, 8, 4, storage);           \
+            case L16x4x4: return UHNSW_STUB(NAME, 16, 4, storage);         \
+            case L32x4x4: return UHNSW_STUB(NAME, 32, 4, storage);         \
+            default: return UHNSW_STUB(NAME, 64, 4, storage);              \
+        }                                                                  \
     }
-}
+UHNSW_STUBS(walk_kernel)
+UHNSW_STUBS(search_kernel)
+#undef UHNSW_STUBS
+#undef UHNSW_STUB
 
 const void *verify_kernel_ptr(int layout) {
     switch (layout) {

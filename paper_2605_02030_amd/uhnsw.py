@@ -20,7 +20,9 @@ STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 
 EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
-           "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info")
+           "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
+           "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
+           "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -44,7 +46,24 @@ class uhnsw_index(ctypes.Structure):
 class uhnsw_params(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("cutoff", ctypes.c_float), ("t", _I32), ("kappa", _I32),
                 ("beam_width", _I32), ("early_abort", _I32), ("visited_slots", _I32),
-                ("waves_per_block", _I32), ("persistent", _I32), ("timing", _I32)]
+                ("waves_per_block", _I32), ("persistent", _I32), ("timing", _I32), ("fused", _I32),
+                ("graph", _I32), ("waves_per_cu", _I32)]
+
+
+class uhnsw_stats(ctypes.Structure):
+    _fields_ = [(f, _I32) for f in ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0")] + \
+               [("t_begin", ctypes.c_uint32), ("t_end", ctypes.c_uint32)]
+
+
+class uhnsw_serve_config(ctypes.Structure):
+    _fields_ = [("k_max", _I32), ("ef_max", _I32), ("max_inflight", _I32), ("max_batch", _I32),
+                ("streams", _I32), ("reserved", _I32), ("hbm_budget", _I64), ("params", uhnsw_params)]
+
+
+class uhnsw_serve_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", _I32), ("nres", _I32), ("submit_us", ctypes.c_double),
+                ("launch_us", ctypes.c_double), ("done_us", ctypes.c_double), ("stats", uhnsw_stats),
+                ("ids", _I64 * UHNSW_KMAX), ("dists", ctypes.c_float * UHNSW_KMAX)]
 
 
 STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end")
@@ -68,6 +87,15 @@ uhnsw_search = _sig("uhnsw_search", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P,
 uhnsw_search_device = _sig("uhnsw_search_device", ctypes.c_int,
                            [_P, _P, _I64, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _I32, _P])
 uhnsw_get_layout = _sig("uhnsw_get_layout", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
+uhnsw_autotune = _sig("uhnsw_autotune", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _I32, _I32, _P, _P])
+uhnsw_graph_captures = _sig("uhnsw_graph_captures", ctypes.c_int, [_P, ctypes.POINTER(_I64)])
+uhnsw_serve_default_config = _sig("uhnsw_serve_default_config", None, [_P])
+uhnsw_serve_start = _sig("uhnsw_serve_start", ctypes.c_int, [_P, _P, ctypes.POINTER(_P)])
+uhnsw_serve_submit = _sig("uhnsw_serve_submit", ctypes.c_int, [_P, _P, ctypes.c_float, _I32, _I32, ctypes.c_uint64])
+uhnsw_serve_poll = _sig("uhnsw_serve_poll", ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)])
+uhnsw_serve_info = _sig("uhnsw_serve_info", ctypes.c_int, [_P, _P])
+uhnsw_serve_drive = _sig("uhnsw_serve_drive", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P])
+uhnsw_serve_stop = _sig("uhnsw_serve_stop", ctypes.c_int, [_P])
 uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
                          [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
@@ -198,6 +226,25 @@ class Context:
             cand_ids.data_ptr() if cand_ids is not None else None,
             cand_keys.data_ptr() if cand_keys is not None else None, cs, stream))
 
+    def autotune(self, queries, p, k, ef, k_max: int, ef_max: int, params: uhnsw_params | None = None,
+                 allow_beam: bool = False, stream=None) -> uhnsw_params:
+        """Time the execution knobs on these device tensors; returns tuned params."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        prm = params if params is not None else default_params()
+        prm = uhnsw_params.from_buffer_copy(prm)
+        self._check(uhnsw_autotune(self.h, queries.data_ptr(), queries.shape[0], p.data_ptr(), k.data_ptr(),
+                                   ef.data_ptr(), int(k_max), int(ef_max), int(allow_beam), ctypes.byref(prm),
+                                   stream))
+        return prm
+
+    def graph_captures(self) -> int:
+        n = _I64()
+        self._check(uhnsw_graph_captures(self.h, ctypes.byref(n)))
+        return n.value
+
     def device_info(self):
         cus, khz = _I32(), _I32()
         self._check(uhnsw_device_info(self.h, ctypes.byref(cus), ctypes.byref(khz)))
@@ -207,3 +254,74 @@ class Context:
         w, v = ctypes.c_float(), ctypes.c_float()
         self._check(uhnsw_last_timing(self.h, ctypes.byref(w), ctypes.byref(v)))
         return w.value, v.value
+
+
+class Server:
+    """Continuous-batching server on a Context (include/uhnsw.h, serving form)."""
+
+    def __init__(self, ctx: Context, **cfg):
+        c = uhnsw_serve_config()
+        uhnsw_serve_default_config(ctypes.byref(c))
+        for key, val in cfg.items():
+            if key == "params":
+                c.params = val
+            else:
+                setattr(c, key, val)
+        h = _P()
+        rc = uhnsw_serve_start(ctx.h, ctypes.byref(c), ctypes.byref(h))
+        if rc != UHNSW_OK:
+            raise UhnswError(rc, "uhnsw_serve_start failed")
+        self.h, self.ctx, self.d, self.cfg = h, ctx, ctx.d, c
+
+    def submit(self, q, p, k, ef, tag) -> int:
+        q = np.ascontiguousarray(q, np.float32)
+        return uhnsw_serve_submit(self.h, q.ctypes.data, float(p), int(k), int(ef), int(tag))
+
+    def poll(self, max_n=256):
+        buf = (uhnsw_serve_result * max_n)()
+        n = _I32()
+        rc = uhnsw_serve_poll(self.h, buf, max_n, ctypes.byref(n))
+        if rc != UHNSW_OK:
+            raise UhnswError(rc, "uhnsw_serve_poll failed")
+        return [buf[i] for i in range(n.value)]
+
+    def info(self):
+        a = np.zeros(8, np.int64)
+        uhnsw_serve_info(self.h, a.ctypes.data)
+        return dict(zip(("slots", "free", "pending", "batches", "completed", "max_overlap", "max_batch",
+                         "streams"), a.tolist()))
+
+    def drive(self, queries, p, k, ef, arrival_us):
+        """Submit on the given schedule, return (ids, dists, status, submit_us, launch_us, done_us)."""
+        queries = np.ascontiguousarray(queries, np.float32)
+        n = queries.shape[0]
+        p = np.ascontiguousarray(p, np.float32)
+        k = np.ascontiguousarray(k, np.int32)
+        ef = np.ascontiguousarray(ef, np.int32)
+        arr = np.ascontiguousarray(arrival_us, np.float64)
+        res = (uhnsw_serve_result * n)()
+        rc = uhnsw_serve_drive(self.h, n, queries.ctypes.data, p.ctypes.data, k.ctypes.data, ef.ctypes.data,
+                               arr.ctypes.data, res)
+        if rc != UHNSW_OK:
+            raise UhnswError(rc, "uhnsw_serve_drive failed")
+        raw = np.frombuffer(res, dtype=np.uint8).reshape(n, ctypes.sizeof(uhnsw_serve_result))
+        off_ids = uhnsw_serve_result.ids.offset
+        off_d = uhnsw_serve_result.dists.offset
+        ids = raw[:, off_ids:off_ids + 8 * UHNSW_KMAX].copy().view(np.int64)
+        dists = raw[:, off_d:off_d + 4 * UHNSW_KMAX].copy().view(np.float32)
+        status = np.array([r.status for r in res], np.int32)
+        t = np.array([(r.submit_us, r.launch_us, r.done_us) for r in res], np.float64)
+        return ids, dists, status, t[:, 0], t[:, 1], t[:, 2]
+
+    def stop(self):
+        if getattr(self, "h", None):
+            rc = uhnsw_serve_stop(self.h)
+            self.h = None
+            if rc != UHNSW_OK:
+                raise UhnswError(rc, "server ended with an error")
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass

@@ -47,8 +47,8 @@ def test_default_params(lib):
 
 
 def test_struct_sizes_match_header(lib):
-    # uhnsw_params: double + float + 8 int32 (+ padding to 8) = 48 bytes
-    assert ctypes.sizeof(lib.uhnsw_params) == 48
+    # uhnsw_params: double + float + 11 int32 = 56 bytes
+    assert ctypes.sizeof(lib.uhnsw_params) == 56
     assert ctypes.sizeof(lib.uhnsw_graph) == 12 + 4 + 8 + 32 * 8 * 4  # M..entry, pad, level ptr, 4 arrays
     assert lib.STATS_DTYPE.itemsize == 40
 

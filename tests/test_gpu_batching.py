@@ -1,0 +1,135 @@
+"""GPU tests of the batching form: one fused walk+verify kernel, persistent
+with a work counter over mixed p / k / ef, captured as a hipGraph, with
+knobs chosen by the autotuner. Results must not depend on any of these."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from test_gpu_parity import compare, run_device, _say  # noqa: E402,F401
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctxb(torch_cuda, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g1, g2)
+    yield c
+    c.close()
+
+
+def _mixed(wl, seed=31):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nq = wl.nq
+    k = np.array([1, 10, 100], np.int32)[np.arange(nq) % 3]
+    ef = np.array([rng.integers(kk, 257) for kk in k], np.int32)
+    p = wl.p.copy()
+    p[:6] = [0.5, 1.0, 1.5, 2.0, 1.4, 0.73]
+    return p, k, ef
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        if x.dtype.names:
+            for f in x.dtype.names:
+                if f not in ("n_b", "t_begin", "t_end"):
+                    np.testing.assert_array_equal(x[f], y[f])
+        else:
+            np.testing.assert_array_equal(x, y)
+
+
+@pytest.mark.parametrize("knobs", [dict(fused=1), dict(fused=1, persistent=1),
+                                   dict(fused=1, persistent=1, waves_per_cu=2),
+                                   dict(fused=1, persistent=1, beam_width=1, visited_slots=256)])
+def test_fused_matches_two_kernels(torch_cuda, ctxb, wl1, knobs):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    p, k, ef = _mixed(wl)
+    a = run_device(torch_cuda, ctxb, wl.queries, p, k, ef, 100, 256)
+    b = run_device(torch_cuda, ctxb, wl.queries, p, k, ef, 100, 256, params=uhnsw.default_params(**knobs))
+    _same(a, b)
+
+
+def test_fused_persistent_parity_mixed(torch_cuda, ctxb, wl1):
+    """Mixed p, K and ef in one persistent fused launch, against the oracle."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    g, v = ctxb.layout()
+    p, k, ef = _mixed(wl, seed=32)
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    gpu = run_device(torch_cuda, ctxb, wl.queries, p, k, ef, 100, 256,
+                     params=uhnsw.default_params(fused=1, persistent=1))
+    compare(wl.base, G1, G2, D, wl.queries, p, k, ef, gpu, g, v)
+
+
+def test_graph_replays(torch_cuda, ctxb, wl1):
+    """Capture once, replay several times with eager work in between; every
+    replay equals the eager result."""
+    from paper_2605_02030_amd import uhnsw
+
+    torch = torch_cuda
+    wl, _, _ = wl1
+    dev = torch.device("cuda:0")
+    p, k, ef = _mixed(wl, seed=33)
+    nq = wl.nq
+    tq = torch.from_numpy(wl.queries).to(dev)
+    tp, tk, te = (torch.from_numpy(x).to(dev) for x in (p, k, ef))
+    eager = run_device(torch, ctxb, wl.queries, p, k, ef, 100, 256, params=uhnsw.default_params(fused=1,
+                                                                                                 persistent=1))
+    ids = torch.empty((nq, 100), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, 100), dtype=torch.float32, device=dev)
+    stats = torch.zeros((nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
+    prm = uhnsw.default_params(fused=1, persistent=1, graph=1)
+    before = ctxb.graph_captures()
+    for rep in range(4):
+        ids.fill_(-7)
+        dists.fill_(-7.0)
+        ctxb.search_device(tq, tp, tk, te, 100, 256, ids, dists, stats, params=prm)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 20, device=dev).sum()
+        assert torch.isfinite(junk)
+        np.testing.assert_array_equal(ids.cpu().numpy(), eager[0])
+        np.testing.assert_array_equal(dists.cpu().numpy(), eager[1])
+        st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(nq)
+        np.testing.assert_array_equal(st["n_p"], eager[2]["n_p"])
+    assert ctxb.graph_captures() == before + 1  # captured once, replayed after
+    # changing an argument re-captures
+    ctxb.search_device(tq, tp, tk, te, 100, 256, ids, dists, stats,
+                       params=uhnsw.default_params(fused=1, persistent=1, graph=1, visited_slots=1024))
+    torch.cuda.synchronize()
+    assert ctxb.graph_captures() == before + 2
+    np.testing.assert_array_equal(ids.cpu().numpy(), eager[0])
+
+
+def test_autotune_result_invariant(torch_cuda, ctxb, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    torch = torch_cuda
+    wl, _, _ = wl1
+    dev = torch.device("cuda:0")
+    p, k, ef = _mixed(wl, seed=34)
+    tq = torch.from_numpy(wl.queries).to(dev)
+    tp, tk, te = (torch.from_numpy(x).to(dev) for x in (p, k, ef))
+    tuned = ctxb.autotune(tq, tp, tk, te, 100, 256, params=uhnsw.default_params(fused=1))
+    _say("autotuned", tuned.visited_slots, tuned.waves_per_block, tuned.persistent, tuned.beam_width)
+    assert tuned.beam_width == 1 and tuned.fused == 1 and tuned.visited_slots in (512, 1024, 2048, 4096)
+    a = run_device(torch, ctxb, wl.queries, p, k, ef, 100, 256)
+    b = run_device(torch, ctxb, wl.queries, p, k, ef, 100, 256, params=tuned)
+    _same(a, b)
+    again = ctxb.autotune(tq, tp, tk, te, 100, 256, params=uhnsw.default_params(fused=1))
+    assert (again.visited_slots, again.waves_per_block, again.persistent) == \
+        (tuned.visited_slots, tuned.waves_per_block, tuned.persistent)  # cached

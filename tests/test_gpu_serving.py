@@ -1,0 +1,107 @@
+"""GPU tests of the serving form (continuous batching): a query's result is
+the same alone, in a Poisson mix, and in a plain batch search; admission
+refuses work beyond its slots (EBUSY) and its HBM budget; batches that
+arrive while others run overlap on the device."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from test_gpu_parity import _say  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctxs(torch_cuda, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g1, g2)
+    yield c
+    c.close()
+
+
+def _stream(wl, n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = rng.integers(0, wl.nq, n)
+    q = wl.queries[idx] + rng.standard_normal((n, wl.d)).astype(np.float32) * 0.05
+    p = (2.0 - 1.5 * rng.random(n)).astype(np.float32)
+    k = np.where(rng.random(n) < 0.5, 10, 100).astype(np.int32)
+    ef = np.maximum(k, 128).astype(np.int32)
+    return q.astype(np.float32), p, k, ef
+
+
+def test_alone_vs_mix_vs_batch(torch_cuda, ctxs, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    q, p, k, ef = _stream(wl, 3000, 41)
+    srv = uhnsw.Server(ctxs, k_max=100, ef_max=128)
+    try:
+        # alone: one query at a time
+        alone = {}
+        for i in (0, 1, 777, 2999):
+            assert srv.submit(q[i], p[i], k[i], ef[i], i) == uhnsw.UHNSW_OK
+            got = []
+            while not got:
+                got = srv.poll()
+            r = got[0]
+            assert r.tag == i and r.status == 0
+            alone[i] = (np.array(r.ids[:k[i]]), np.array(r.dists[:k[i]]))
+        # in a mix: Poisson arrivals at 200k/s
+        rng = np.random.Generator(np.random.PCG64(42))
+        arrival = np.cumsum(rng.exponential(1e6 / 200_000, len(p)))
+        ids, dists, status, t_sub, t_launch, t_done = srv.drive(q, p, k, ef, arrival)
+        info = srv.info()
+    finally:
+        srv.stop()
+    _say("serving info", info)
+    assert (status == 0).all()
+    assert info["max_overlap"] >= 2  # batches overlapped on the device
+    assert (t_done >= t_launch).all() and (t_launch >= t_sub - 1.0).all()
+    for i, (ai, ad) in alone.items():
+        np.testing.assert_array_equal(ids[i, :k[i]], ai)
+        np.testing.assert_array_equal(dists[i, :k[i]], ad)
+    # and equal to one plain batch launch of all queries
+    ref_ids, ref_d, _ = ctxs.search(q, p, k, ef, params=uhnsw.default_params(fused=1), k_stride=100)
+    for i in range(len(p)):
+        np.testing.assert_array_equal(ids[i, :k[i]], ref_ids[i, :k[i]])
+        np.testing.assert_array_equal(dists[i, :k[i]], ref_d[i, :k[i]])
+    lat = t_done - t_sub
+    _say(f"latency p50 {np.percentile(lat, 50):.0f} us p99 {np.percentile(lat, 99):.0f} us")
+
+
+def test_admission_busy_and_budget(torch_cuda, ctxs, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    q, p, k, ef = _stream(wl, 40, 43)
+    srv = uhnsw.Server(ctxs, k_max=100, ef_max=128, max_inflight=4, streams=2)
+    try:
+        rcs = [srv.submit(q[i], p[i], k[i], ef[i], i) for i in range(40)]
+        assert uhnsw.UHNSW_EBUSY in rcs
+        accepted = [i for i, rc in enumerate(rcs) if rc == uhnsw.UHNSW_OK]
+        assert 1 <= len(accepted) <= 40
+        got = []
+        while len(got) < len(accepted):
+            got += srv.poll()
+        assert sorted(r.tag for r in got) == accepted
+        # slots are free again
+        assert srv.submit(q[0], p[0], k[0], ef[0], 99) == uhnsw.UHNSW_OK
+        while not srv.poll():
+            pass
+        assert srv.submit(q[0], 0.3, k[0], ef[0], 1) == uhnsw.UHNSW_EINVAL
+        assert srv.submit(q[0], p[0], 101, 128, 1) == uhnsw.UHNSW_EINVAL
+    finally:
+        srv.stop()
+    with pytest.raises(uhnsw.UhnswError) as e:
+        uhnsw.Server(ctxs, k_max=100, ef_max=128, hbm_budget=64)
+    assert e.value.code == uhnsw.UHNSW_EBUSY
