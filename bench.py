@@ -203,6 +203,103 @@ def cpu_baseline(wl, g1, g2, ef, budget_s=15.0):
                 sample=f"first {n} of {wl.nq} queries, ef={ef}, same graphs/params, {dt:.1f}s wall")
 
 
+def gt_for(wl):
+    path = os.path.join(ROOT, "tests", "golden", f"gt_{wl.name}.npz")
+    gt = dict(np.load(path))
+    if bytes(gt["digest"]).decode() != wl.digest():
+        raise SystemExit(f"{path} does not match the generated workload")
+    return gt
+
+
+def lp_dist64(base, q, ids, p):
+    x = base[ids].astype(np.float64)
+    return (np.abs(x - q.astype(np.float64)) ** float(p)).sum(1) ** (1.0 / float(p))
+
+
+def run_secondary(a, torch, uhnsw, sg, synth):
+    """Workload 3 (precision form) or 4 (batching form): one JSON line."""
+    wl = synth.make_workload(a.workload)
+    log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq}")
+    gt = gt_for(wl)
+    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(wl.queries).to(dev)
+    p = torch.from_numpy(wl.p).to(dev)
+    k = torch.from_numpy(wl.k).to(dev)
+    kmax = int(wl.k.max())
+    ids = torch.empty((wl.nq, kmax), dtype=torch.int64, device=dev)
+    dists = torch.empty((wl.nq, kmax), dtype=torch.float32, device=dev)
+    stats = torch.zeros((wl.nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
+    out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries": wl.nq, "forms": {}}
+
+    def timed_run(ctx, ef_t, efmax, prm, steps):
+        for _ in range(2):
+            ctx.search_device(q, p, k, ef_t, kmax, efmax, ids, dists, stats, params=prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.search_device(q, p, k, ef_t, kmax, efmax, ids, dists, stats, params=prm)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    def quality(ids_np, dists_np):
+        got = ids_np[gt["qidx"], :10]
+        rec = float(np.mean([len(set(got[i].tolist()) & set(gt["ids"][i].tolist())) / 10
+                             for i in range(len(got))]))
+        err = 0.0
+        for i in gt["qidx"][:50]:
+            kk = int(wl.k[i])
+            sel = ids_np[i, :kk]
+            d64 = lp_dist64(wl.base, wl.queries[i], sel, wl.p[i])
+            err = max(err, float(np.max(np.abs(dists_np[i, :kk] - d64) / d64)))
+        return rec, err
+
+    if a.workload == 4:
+        ef_t = torch.from_numpy(wl.ef).to(dev)
+        efmax = int(wl.ef.max())
+        for name, batched in (("plain", False), ("batched", True)):
+            ctx = uhnsw.Context(0)
+            ctx.load_graphs(wl.base, g1, g2)
+            if batched:
+                prm = ctx.autotune(q, p, k, ef_t, kmax, efmax,
+                                   params=uhnsw.default_params(fused=1, persistent=1), allow_beam=True)
+                prm.graph = 1
+                knobs = dict(beam=prm.beam_width, slots=prm.visited_slots, wpb=prm.waves_per_block,
+                             persistent=prm.persistent)
+            else:
+                prm = uhnsw.default_params()
+                knobs = {}
+            dt = timed_run(ctx, ef_t, efmax, prm, a.steps)
+            rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
+            st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(wl.nq)
+            lat = ((st["t_end"].astype(np.int64) - st["t_begin"].astype(np.int64).min()) % (1 << 32)) / \
+                ctx.device_info()[1]
+            out["forms"][name] = dict(qps=round(wl.nq / dt, 1), ms_per_launch=round(dt * 1e3, 3),
+                                      recall_at_10=round(rec, 4), max_rel_dist_err=err,
+                                      p50_ms=round(float(np.percentile(lat, 50)), 3),
+                                      p99_ms=round(float(np.percentile(lat, 99)), 3), **knobs)
+            log(name, json.dumps(out["forms"][name]))
+            ctx.close()
+    else:
+        for name, storage in (("fp32", uhnsw.STORE_F32), ("bf16", uhnsw.STORE_BF16), ("fp16", uhnsw.STORE_F16)):
+            ctx = uhnsw.Context(0)
+            ctx.load_graphs(wl.base, g1, g2, storage=storage)
+            sweep = []
+            for ef in EF_GRID:
+                ef_t = torch.full((wl.nq,), ef, dtype=torch.int32, device=dev)
+                prm = uhnsw.default_params(fused=1)
+                dt = timed_run(ctx, ef_t, ef, prm, a.steps)
+                rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
+                sweep.append(dict(ef=ef, qps=round(wl.nq / dt, 1), recall_at_10=round(rec, 4),
+                                  max_rel_dist_err=err))
+                log(name, json.dumps(sweep[-1]))
+            ok = [s for s in sweep if s["recall_at_10"] >= TARGET_RECALL]
+            best = max(ok, key=lambda s: s["qps"]) if ok else max(sweep, key=lambda s: s["recall_at_10"])
+            out["forms"][name] = dict(best=best, sweep=sweep)
+            ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,6 +309,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4),
+                    help="2: the headline workload; 3: precision form; 4: batching form")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()
@@ -227,6 +326,9 @@ def main():
     from paper_2605_02030_amd import uhnsw
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.workload != 2:
+        run_secondary(a, torch, uhnsw, sg, synth)
+        return
     t0 = time.time()
     wl = synth.make_workload(2)
     log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq} ({time.time() - t0:.1f}s)")

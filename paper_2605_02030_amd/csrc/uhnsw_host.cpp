@@ -41,7 +41,7 @@ struct DevBuf {
 };
 
 struct GraphKey {
-    const void *ptrs[9];
+    const void *ptrs[16];
     int64_t nq;
     int32_t ints[4];
     uhnsw_params prm;
@@ -80,6 +80,23 @@ struct uhnsw_ctx {
     hipGraphExec_t gexec = nullptr;
     GraphKey gkey{};
     int64_t graph_captures = 0;
+    // host-pointer path under a hipGraph: pinned staging + the captured
+    // sequence H2D copies -> kernels -> D2H copies
+    struct Pinned {
+        void *p = nullptr;
+        size_t bytes = 0;
+    } hp[7];
+    hipGraphExec_t hgexec = nullptr;
+    GraphKey hgkey{};
+    // resident blocks per CU by (kernel, block size, LDS bytes), queried once
+    // (also keeps the query out of any hipGraph capture)
+    struct Occ {
+        const void *kernel;
+        int block;
+        size_t lds;
+        int per_cu;
+    };
+    std::vector<Occ> occ;
     // autotuner results keyed by (n, d, storage, ef bucket, k_max, beam, fused)
     std::vector<std::pair<uint64_t, uhnsw_params>> tuned;
 };
@@ -316,6 +333,9 @@ void uhnsw_destroy(uhnsw_ctx *c) {
         g.up_adj.reset();
     }
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->hgexec) (void)hipGraphExecDestroy(c->hgexec);
+    for (auto &h : c->hp)
+        if (h.p) (void)hipHostFree(h.p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -500,7 +520,16 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
         const void *kp =
             prm.fused ? search_kernel_ptr(c->layout, c->storage) : walk_kernel_ptr(c->layout, c->storage);
         const size_t lds_block = (size_t)(prm.fused ? pl.search_bytes : pl.walk_bytes) * pl.wpb;
-        HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, pl.wpb * kWave, lds_block));
+        bool found = false;
+        for (auto &o : c->occ)
+            if (o.kernel == kp && o.block == pl.wpb * kWave && o.lds == lds_block) {
+                per_cu = o.per_cu;
+                found = true;
+            }
+        if (!found) {
+            HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, pl.wpb * kWave, lds_block));
+            c->occ.push_back({kp, pl.wpb * kWave, lds_block, per_cu});
+        }
         per_cu = std::max(per_cu, 1);
         if (prm.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, prm.waves_per_cu / pl.wpb));
         pgrid = std::max(1, std::min(grid_all, per_cu * c->num_cus));
@@ -663,7 +692,7 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
 }
 
 int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                 const int32_t *ef, const uhnsw_params *prm, int32_t k_stride, int64_t *ids, float *dists,
+                 const int32_t *ef, const uhnsw_params *prm_in, int32_t k_stride, int64_t *ids, float *dists,
                  uhnsw_stats *stats) {
     if (!c) return UHNSW_EINVAL;
     if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
@@ -696,18 +725,93 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     HIP_OR_FAIL(c, c->s_dists.ensure(nqs * k_stride * 4));
     HIP_OR_FAIL(c, c->s_stats.ensure(nqs * sizeof(uhnsw_stats)));
     hipStream_t s = c->stream;
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_q.p, queries, nqs * c->d * 4, hipMemcpyHostToDevice, s));
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_p.p, p, nqs * 4, hipMemcpyHostToDevice, s));
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_k.p, k, nqs * 4, hipMemcpyHostToDevice, s));
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->s_ef.p, ef, nqs * 4, hipMemcpyHostToDevice, s));
-    int r = uhnsw_search_device(c, c->s_q.as<float>(), nq, c->s_p.as<float>(), c->s_k.as<int32_t>(),
-                                c->s_ef.as<int32_t>(), k_max, ef_max, prm, k_stride, c->s_ids.as<int64_t>(),
-                                c->s_dists.as<float>(), c->s_stats.as<uhnsw_stats>(), nullptr, nullptr, 0, s);
-    if (r) return r;
-    HIP_OR_FAIL(c, hipMemcpyAsync(ids, c->s_ids.p, nqs * k_stride * 8, hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(c, hipMemcpyAsync(dists, c->s_dists.p, nqs * k_stride * 4, hipMemcpyDeviceToHost, s));
-    if (stats) HIP_OR_FAIL(c, hipMemcpyAsync(stats, c->s_stats.p, nqs * sizeof(uhnsw_stats), hipMemcpyDeviceToHost, s));
-    HIP_OR_FAIL(c, hipStreamSynchronize(s));
+    uhnsw_params prm;
+    if (prm_in)
+        prm = *prm_in;
+    else
+        uhnsw_default_params(&prm);
+    const size_t bytes[7] = {nqs * c->d * 4, nqs * 4, nqs * 4, nqs * 4, nqs * k_stride * 8, nqs * k_stride * 4,
+                             nqs * sizeof(uhnsw_stats)};
+    void *dev[7] = {c->s_q.p, c->s_p.p, c->s_k.p, c->s_ef.p, c->s_ids.p, c->s_dists.p, c->s_stats.p};
+    // the search through one set of host buffers: 4 copies in, kernels, 3 out
+    auto enqueue = [&](hipStream_t st, void *const *host, const uhnsw_params &pr) -> int {
+        for (int i = 0; i < 4; ++i) HIP_OR_FAIL(c, hipMemcpyAsync(dev[i], host[i], bytes[i], hipMemcpyHostToDevice, st));
+        int r = uhnsw_search_device(c, c->s_q.as<float>(), nq, c->s_p.as<float>(), c->s_k.as<int32_t>(),
+                                    c->s_ef.as<int32_t>(), k_max, ef_max, &pr, k_stride, c->s_ids.as<int64_t>(),
+                                    c->s_dists.as<float>(), c->s_stats.as<uhnsw_stats>(), nullptr, nullptr, 0, st);
+        if (r) return r;
+        for (int i = 4; i < 7; ++i) {
+            if (i == 6 && !stats) break;
+            HIP_OR_FAIL(c, hipMemcpyAsync(host[i], dev[i], bytes[i], hipMemcpyDeviceToHost, st));
+        }
+        return UHNSW_OK;
+    };
+    if (!prm.graph) {
+        const void *user_in[4] = {queries, p, k, ef};
+        void *host[7] = {const_cast<void *>(user_in[0]), const_cast<void *>(user_in[1]),
+                         const_cast<void *>(user_in[2]), const_cast<void *>(user_in[3]), ids, dists, stats};
+        int r = enqueue(s, host, prm);
+        if (r) return r;
+        HIP_OR_FAIL(c, hipStreamSynchronize(s));
+        return UHNSW_OK;
+    }
+    // hipGraph: stage through pinned buffers so the captured copies stay valid
+    bool grown = false;
+    for (int i = 0; i < 7; ++i) {
+        if (c->hp[i].bytes >= bytes[i] && c->hp[i].p) continue;
+        if (c->hp[i].p) (void)hipHostFree(c->hp[i].p);
+        c->hp[i].p = nullptr;
+        c->hp[i].bytes = 0;
+        HIP_OR_FAIL(c, hipHostMalloc(&c->hp[i].p, bytes[i] ? bytes[i] : 1, hipHostMallocDefault));
+        c->hp[i].bytes = bytes[i];
+        grown = true;
+    }
+    void *host[7];
+    for (int i = 0; i < 7; ++i) host[i] = c->hp[i].p;
+    std::memcpy(host[0], queries, bytes[0]);
+    std::memcpy(host[1], p, bytes[1]);
+    std::memcpy(host[2], k, bytes[2]);
+    std::memcpy(host[3], ef, bytes[3]);
+    uhnsw_params pr = prm;
+    pr.graph = 0;
+    pr.timing = 0;
+    GraphKey key{};
+    for (int i = 0; i < 7; ++i) key.ptrs[i] = host[i];
+    for (int i = 0; i < 7; ++i) key.ptrs[7 + i] = dev[i];
+    key.ptrs[14] = stats ? stats : nullptr;  // whether stats are copied out
+    key.nq = nq;
+    key.ints[0] = k_max;
+    key.ints[1] = ef_max;
+    key.ints[2] = k_stride;
+    key.prm = pr;
+    if (c->hgexec && !grown && std::memcmp(&key, &c->hgkey, sizeof key) == 0) {
+        HIP_OR_FAIL(c, hipGraphLaunch(c->hgexec, s));
+        HIP_OR_FAIL(c, hipStreamSynchronize(s));
+    } else {
+        // first call with this shape: run it, then capture the same sequence
+        int r = enqueue(s, host, pr);
+        if (r) return r;
+        HIP_OR_FAIL(c, hipStreamSynchronize(s));
+        if (c->hgexec) {
+            (void)hipGraphExecDestroy(c->hgexec);
+            c->hgexec = nullptr;
+        }
+        if (!c->cap_stream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIP_OR_FAIL(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        r = enqueue(c->cap_stream, host, pr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+        if (r) return r;
+        if (e2 != hipSuccess) return dev_fail(c, e2, "hipStreamEndCapture (host path)");
+        hipError_t e = hipGraphInstantiate(&c->hgexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate (host path)");
+        c->hgkey = key;
+        ++c->graph_captures;
+    }
+    std::memcpy(ids, host[4], bytes[4]);
+    std::memcpy(dists, host[5], bytes[5]);
+    if (stats) std::memcpy(stats, host[6], bytes[6]);
     return UHNSW_OK;
 }
 

@@ -1,12 +1,16 @@
-"""Write the exact L_p ground truth used for recall@10 on the 1M x 128
-mixture workload: tests/golden/gt_mixture-1M-d128.npz.
+"""Write the exact L_p ground truth used for recall@10:
+tests/golden/gt_<workload>.npz.
 
 Calls only the oracle's brute force (FP64, ties by smaller id; the recall
 definition of the U-HNSW paper, Sec. 4.1.2) on the seeded inputs from
-``synth``. The sample is every 5th query (2,000 of 10,000): 5 is coprime to
-the 16-value p grid, so each p in {0.5, ..., 2.0} appears 125 times.
+``synth``. Samples:
+  workload 2 (mixture-1M-d128): every 5th query (2,000 of 10,000); 5 is
+      coprime to the 16-value p grid, so each p appears 125 times;
+  workload 3 (gammafeat-1M-d960): every 10th query (100 of 1,000);
+  workload 4 (unitgauss-1.18M-d100): every 30th query starting at 1 (the
+      K = 10 queries; 334 of 10,000).
 
-    python tests/golden/make_groundtruth.py [--threads N]
+    python tests/golden/make_groundtruth.py [--workload 2|3|4] [--threads N]
 """
 import argparse
 import os
@@ -21,28 +25,31 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gt_mixture-1M-d128.npz")
-STRIDE = 5
+HERE = os.path.dirname(os.path.abspath(__file__))
+SAMPLE = {2: (0, 5), 3: (0, 10), 4: (1, 30)}  # workload -> (first query, stride)
 K = 10
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--workload", type=int, default=2, choices=sorted(SAMPLE))
     a = ap.parse_args()
-    wl = synth.make_workload(2)
-    qidx = np.arange(0, wl.nq, STRIDE, dtype=np.int32)
+    wl = synth.make_workload(a.workload)
+    first, stride = SAMPLE[a.workload]
+    qidx = np.arange(first, wl.nq, stride, dtype=np.int32)
+    out = os.path.join(HERE, f"gt_{wl.name}.npz")
     t0 = time.time()
     ids = np.empty((len(qidx), K), np.int32)
     S = np.empty((len(qidx), K), np.float64)
-    step = 100
+    step = 50
     for s in range(0, len(qidx), step):
         sel = qidx[s:s + step]
         ids[s:s + step], S[s:s + step] = oracle.bruteforce(wl.base, wl.queries[sel], wl.p[sel], K, a.threads)
         print(f"{s + len(sel)}/{len(qidx)} queries, {time.time() - t0:.0f}s", flush=True)
-    np.savez(OUT, qidx=qidx, ids=ids, S=S, p=wl.p[qidx], K=np.int32(K),
+    np.savez(out, qidx=qidx, ids=ids, S=S, p=wl.p[qidx], K=np.int32(K),
              digest=np.frombuffer(wl.digest().encode(), np.uint8))
-    print("wrote", OUT)
+    print("wrote", out)
 
 
 if __name__ == "__main__":

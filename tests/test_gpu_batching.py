@@ -133,3 +133,29 @@ def test_autotune_result_invariant(torch_cuda, ctxb, wl1):
     again = ctxb.autotune(tq, tp, tk, te, 100, 256, params=uhnsw.default_params(fused=1))
     assert (again.visited_slots, again.waves_per_block, again.persistent) == \
         (tuned.visited_slots, tuned.waves_per_block, tuned.persistent)  # cached
+
+
+def test_host_path_graph_with_copies(torch_cuda, ctxb, wl1):
+    """Host-pointer search under a hipGraph: copies in, kernels, copies out are
+    captured once per shape and replayed; each call's results equal the
+    uncaptured search of the same queries."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl1
+    p, k, ef = _mixed(wl, seed=35)
+    prm_g = uhnsw.default_params(fused=1, persistent=1, graph=1)
+    prm_e = uhnsw.default_params(fused=1, persistent=1)
+    before = ctxb.graph_captures()
+    halves = (slice(0, 50), slice(50, 100))
+    for rep in range(2):
+        for sl in halves:  # same shape, different inputs: replay
+            a = ctxb.search(wl.queries[sl], p[sl], k[sl], ef[sl], params=prm_g, k_stride=100)
+            b = ctxb.search(wl.queries[sl], p[sl], k[sl], ef[sl], params=prm_e, k_stride=100)
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[1], b[1])
+            np.testing.assert_array_equal(a[2]["n_p"], b[2]["n_p"])
+    assert ctxb.graph_captures() == before + 1
+    c = ctxb.search(wl.queries[:37], p[:37], k[:37], ef[:37], params=prm_g, k_stride=100)  # new shape
+    d = ctxb.search(wl.queries[:37], p[:37], k[:37], ef[:37], params=prm_e, k_stride=100)
+    np.testing.assert_array_equal(c[0], d[0])
+    assert ctxb.graph_captures() == before + 2

@@ -1,0 +1,142 @@
+"""GPU parity on the shapes of the five workloads.
+
+* The benchmark workload (1M x 128 mixture, 10,000 queries) at full size in
+  the launch configurations bench.py times, compared with the oracle on a
+  sample of queries it computes one by one; recall@10 against the stored
+  FP64 ground truth.
+* The precision form (d = 960 gamma features; BF16 and FP16 walk storage,
+  FP32 re-rank) and the batching form (d = 100 unit vectors, K in {1, 10,
+  100}, ef in [K, 512]) at reduced n with the full dimension.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import synth.graphs as sg  # noqa: E402
+from test_gpu_parity import compare, run_device, _say  # noqa: E402
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.fixture(scope="module")
+def wl2_full():
+    _say("workload 2 full size: generating inputs and graphs (cached when present)")
+    wl = synth.make_workload(2)
+    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+    sys.stdout.flush()
+    return wl, g1, g2
+
+
+def _sample_compare(torch, ctx, wl, g1, g2, ef, params, storage, sample, w=1):
+    """All queries on the GPU; the sample compared with the oracle."""
+    from paper_2605_02030_amd import uhnsw
+
+    g, v = ctx.layout()
+    efa = np.full(wl.nq, ef, np.int32)
+    ids, dists, st, cid, ckey = run_device(torch, ctx, wl.queries, wl.p, wl.k, efa, 10, ef, params=params)
+    G1, G2 = oracle.Graph(g1), oracle.Graph(g2)
+    D = oracle.Data(wl.base, storage=storage)
+    sub = (ids[sample], dists[sample], st[sample], cid[sample], ckey[sample])
+    compare(wl.base, G1, G2, D, wl.queries[sample], wl.p[sample], wl.k[sample], efa[sample], sub, g, v, w=w)
+    assert (st["flags"] == 0).all()
+    return ids
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_bench_configurations(torch_cuda, wl2_full):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl2_full
+    gt = dict(np.load(os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")))
+    assert bytes(gt["digest"]).decode() == wl.digest()
+    sample = np.arange(3, wl.nq, 211)  # 48 queries, all 16 p values
+    ef = 256
+    # plain FP32 form: two kernels, default knobs
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2)
+    ids = _sample_compare(torch_cuda, ctx, wl, g1, g2, ef, None, oracle.F32, sample)
+    ctx.close()
+    got = ids[gt["qidx"], :10]
+    rec = np.mean([len(set(got[i].tolist()) & set(gt["ids"][i].tolist())) / 10 for i in range(len(got))])
+    _say(f"full-size FP32 recall@10 = {rec:.4f}")
+    assert rec >= 0.9
+    # batched form: BF16 walk, fused persistent launch, beam width 2
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16)
+    prm = uhnsw.default_params(fused=1, persistent=1, beam_width=2, visited_slots=1024)
+    ids2 = _sample_compare(torch_cuda, ctx, wl, g1, g2, ef, prm, oracle.BF16, sample, w=2)
+    ctx.close()
+    got = ids2[gt["qidx"], :10]
+    rec2 = np.mean([len(set(got[i].tolist()) & set(gt["ids"][i].tolist())) / 10 for i in range(len(got))])
+    _say(f"full-size BF16 batched recall@10 = {rec2:.4f}")
+    assert rec2 >= 0.9
+
+
+@pytest.fixture(scope="module")
+def wl3_small():
+    wl = synth.make_workload(3, n=20_000, nq=48)
+    g1, g2 = sg.build_graphs(wl, cache=False)
+    return wl, g1, g2
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+def test_precision_form_d960(torch_cuda, wl3_small, storage):
+    """d = 960 rows (layout 64 lanes x 4 x 4 chunks, pitch 1024); BF16 / FP16
+    walk with FP32 re-rank: C equals the oracle walking the same storage and
+    distances stay within 1e-5 of FP64."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl3_small
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2, storage=storage)
+    g, v = ctx.layout()
+    assert (g, v) == (64, 4)
+    efa = np.full(wl.nq, 128, np.int32)
+    gpu = run_device(torch_cuda, ctx, wl.queries, wl.p, wl.k, efa, 10, 128)
+    gpu_f = run_device(torch_cuda, ctx, wl.queries, wl.p, wl.k, efa, 10, 128,
+                       params=uhnsw.default_params(fused=1, persistent=1))
+    ctx.close()
+    for a, b in zip(gpu[:2], gpu_f[:2]):
+        np.testing.assert_array_equal(a, b)
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base, storage=storage)
+    compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, efa, gpu, g, v)
+
+
+@pytest.fixture(scope="module")
+def wl4_small():
+    wl = synth.make_workload(4, n=30_000, nq=300)
+    g1, g2 = sg.build_graphs(wl, cache=False)
+    return wl, g1, g2
+
+
+def test_batching_form_d100_mixed(torch_cuda, wl4_small):
+    """d = 100 (pitch padded to 128 with zeros), K in {1, 10, 100}, ef in
+    [K, 512], one fused persistent launch against the oracle."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl4_small
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2)
+    g, v = ctx.layout()
+    gpu = run_device(torch_cuda, ctx, wl.queries, wl.p, wl.k, wl.ef, 100, 512,
+                     params=uhnsw.default_params(fused=1, persistent=1))
+    plain = run_device(torch_cuda, ctx, wl.queries, wl.p, wl.k, wl.ef, 100, 512)
+    ctx.close()
+    for a, b in zip(gpu[:2], plain[:2]):
+        np.testing.assert_array_equal(a, b)
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v)
