@@ -778,7 +778,7 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     GraphKey key{};
     for (int i = 0; i < 7; ++i) key.ptrs[i] = host[i];
     for (int i = 0; i < 7; ++i) key.ptrs[7 + i] = dev[i];
-    key.ptrs[14] = stats ? stats : nullptr;  // whether stats are copied out
+    key.ptrs[14] = reinterpret_cast<const void *>(stats ? 1 : 0);  // whether stats are copied out
     key.nq = nq;
     key.ints[0] = k_max;
     key.ints[1] = ef_max;
