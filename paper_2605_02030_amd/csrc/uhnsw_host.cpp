@@ -218,20 +218,25 @@ int upload_graph(uhnsw_ctx *c, const uhnsw_graph &g, int64_t n, GraphDev &gd) {
 }
 
 struct Plan {
-    int ef_cap, vis_bits, kv_cap, wpb, walk_bytes, verify_bytes, search_bytes;
+    int ef_cap, vis_bits, vis_kbits, kv_cap, wpb, walk_bytes, verify_bytes, search_bytes;
 };
 
 int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan *pl) {
     pl->ef_cap = round_up(std::max(ef_max, 1), 4);
     int slots = prm.visited_slots;
-    if (slots <= 0) slots = ef_max <= 256 ? 1024 : ef_max <= 512 ? 2048 : 4096;
+    if (slots <= 0) slots = ef_max <= 256 ? 2048 : ef_max <= 512 ? 4096 : 8192;
     int bits = 0;
     while ((1 << bits) < slots) ++bits;
     if (bits < 6 || bits > 14) return fail(c, UHNSW_EINVAL, "visited_slots %d outside [64, 16384]", slots);
     pl->vis_bits = bits;
+    // 16-bit quotient slots when the id width allows (see VisCache)
+    int kbits = 1;
+    while (kbits < 31 && ((int64_t)1 << kbits) < c->n) ++kbits;
+    if (kbits < bits + 1) kbits = bits + 1;
+    pl->vis_kbits = (kbits - bits <= 15) ? kbits : 0;
     const int kappa_max = prm.kappa > 0 ? prm.kappa : std::max(k_max, 2);
     pl->kv_cap = round_up(std::max(k_max, kappa_max), 4);
-    pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits);
+    pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits, pl->vis_kbits);
     pl->verify_bytes = verify_lds_bytes(pl->kv_cap);
     // fused kernel: the verification's arrays follow the walk's list W
     pl->search_bytes = std::max(pl->walk_bytes, pl->ef_cap * 8 + pl->verify_bytes);
@@ -480,6 +485,7 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     a.mtab = c->mtab.as<int32_t>();
     a.ef_cap = pl.ef_cap;
     a.vis_bits = pl.vis_bits;
+    a.vis_kbits = pl.vis_kbits;
     a.kv_cap = pl.kv_cap;
     a.waves_per_block = pl.wpb;
     a.ids = ids;

@@ -58,7 +58,7 @@ struct SearchArgs {
     int32_t t_param, kappa_param, beam, early_abort;
     const int32_t *mtab;    // [UHNSW_KMAX + 1]: ceil(tau * K)
     // LDS plan (per wave)
-    int32_t ef_cap, vis_bits, kv_cap, lds_wave_bytes, waves_per_block;
+    int32_t ef_cap, vis_bits, vis_kbits, kv_cap, lds_wave_bytes, waves_per_block;
     // candidate lists (walk -> verify)
     int32_t *cand_ids;
     float *cand_keys;
@@ -80,7 +80,7 @@ hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t 
 hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
-int walk_lds_bytes(int ef_cap, int vis_bits);
+int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits);
 int verify_lds_bytes(int kv_cap);
 const void *walk_kernel_ptr(int layout, int storage);
 const void *verify_kernel_ptr(int layout);

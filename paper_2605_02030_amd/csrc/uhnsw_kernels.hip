@@ -290,30 +290,73 @@ __device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const
     return nn < cap ? nn : cap;
 }
 
-__device__ __forceinline__ uint32_t vis_slot(int32_t id, int bits) {
-    return ((uint32_t)id * 2654435761u) >> (32 - bits);
-}
+// Visited cache: a direct-mapped table in LDS that never reports a node as
+// visited unless it was (it may forget; duplicates are then dropped against
+// W). Two slot formats:
+//  * 32-bit slots holding the id (-1 empty), slot = multiplicative hash;
+//  * 16-bit slots when ids fit in kbits <= bits + 15: h = id * odd mod 2^kbits
+//    is a bijection on kbits-bit values, the top `bits` of h pick the slot and
+//    the remaining bits + 1 are stored (0 empty) -- slot and stored value
+//    together identify the id, so the table is still exact, at half the LDS
+//    per slot.
+struct VisCache {
+    void *base;
+    int bits, kbits;
+
+    __device__ __forceinline__ void clear(int lane) const {
+        const int words = kbits ? (1 << bits) / 2 : (1 << bits);
+        const int32_t fill = kbits ? 0 : -1;
+        int32_t *w = reinterpret_cast<int32_t *>(base);
+        for (int i = lane; i < words; i += kWave) w[i] = fill;
+    }
+    __device__ __forceinline__ void locate(int32_t id, uint32_t &slot, uint32_t &tag) const {
+        if (kbits) {
+            const uint32_t h = ((uint32_t)id * 0x9E3779B1u) & ((kbits == 32 ? 0u : (1u << kbits)) - 1u);
+            slot = h >> (kbits - bits);
+            tag = (h & ((1u << (kbits - bits)) - 1u)) + 1u;
+        } else {
+            slot = ((uint32_t)id * 2654435761u) >> (32 - bits);
+            tag = (uint32_t)id;
+        }
+    }
+    __device__ __forceinline__ bool seen(uint32_t slot, uint32_t tag) const {
+        return kbits ? reinterpret_cast<const uint16_t *>(base)[slot] == (uint16_t)tag
+                     : reinterpret_cast<const uint32_t *>(base)[slot] == tag;
+    }
+    __device__ __forceinline__ void mark(uint32_t slot, uint32_t tag) const {
+        if (kbits)
+            reinterpret_cast<uint16_t *>(base)[slot] = (uint16_t)tag;
+        else
+            reinterpret_cast<uint32_t *>(base)[slot] = tag;
+    }
+};
 
 // ------------------------------------------------------------------- walk
 struct WalkLds {
     float *Wk;
     uint32_t *Wi;
-    int32_t *vis;
+    VisCache vis;
     int32_t *Uid;
     float *Uk;
     int32_t *Ulo, *Urank, *Slo;
 };
 
-__host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits) {
-    return ef_cap * 8 + (1 << vis_bits) * 4 + kUCap * 4 * 5;
+__host__ __device__ inline int vis_bytes_impl(int vis_bits, int vis_kbits) {
+    return (1 << vis_bits) * (vis_kbits ? 2 : 4);
 }
 
-__device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits) {
+__host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits, int vis_kbits) {
+    return ef_cap * 8 + vis_bytes_impl(vis_bits, vis_kbits) + kUCap * 4 * 5;
+}
+
+__device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kbits) {
     WalkLds L;
     L.Wk = reinterpret_cast<float *>(p);
     L.Wi = reinterpret_cast<uint32_t *>(L.Wk + ef_cap);
-    L.vis = reinterpret_cast<int32_t *>(L.Wi + ef_cap);
-    L.Uid = L.vis + (1 << vis_bits);
+    L.vis.base = L.Wi + ef_cap;
+    L.vis.bits = vis_bits;
+    L.vis.kbits = vis_kbits;
+    L.Uid = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(L.vis.base) + vis_bytes_impl(vis_bits, vis_kbits));
     L.Uk = reinterpret_cast<float *>(L.Uid + kUCap);
     L.Ulo = reinterpret_cast<int32_t *>(L.Uk + kUCap);
     L.Urank = L.Ulo + kUCap;
@@ -330,7 +373,7 @@ template <int G, int NCH, typename T>
 __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
-    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits);
+    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits, A.vis_kbits);
     const float p = A.p[qi];
     const int K = A.k[qi];
     const int ef = A.ef[qi];
@@ -378,8 +421,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
                 qv[c][e] = j < A.d ? q[j] : 0.0f;
             }
     }
-    const int vslots = 1 << A.vis_bits;
-    for (int i = lane; i < vslots; i += kWave) L.vis[i] = -1;
+    L.vis.clear(lane);
 
     // ---- descent over layers max_level .. 1 (greedy, smallest (key, id))
     int32_t cur = Gr.entry;
@@ -418,7 +460,9 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     if (lane == 0) {
         L.Wk[0] = kcur;
         L.Wi[0] = (uint32_t)cur;
-        L.vis[vis_slot(cur, A.vis_bits)] = cur;
+        uint32_t s0, t0;
+        L.vis.locate(cur, s0, t0);
+        L.vis.mark(s0, t0);
     }
     wave_sync();
     int nW = 1, lb = 0, n_exp = 0, flags = 0;
@@ -477,13 +521,13 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
             nb = Gr.adj0[(int64_t)(which == 0 ? node0 : node1) * M0 + slot];
         }
         bool fresh = false;
-        uint32_t vs = 0;
+        uint32_t vs = 0, vt = 0;
         if (nb >= 0) {
-            vs = vis_slot(nb, A.vis_bits);
-            fresh = L.vis[vs] != nb;
+            L.vis.locate(nb, vs, vt);
+            fresh = !L.vis.seen(vs, vt);
         }
         wave_sync();
-        if (fresh) L.vis[vs] = nb;
+        if (fresh) L.vis.mark(vs, vt);
         const uint64_t fm = ballot(fresh);
         const int nnew = popc64(fm);
         if (nnew == 0) continue;
@@ -753,7 +797,7 @@ search_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
-    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits);
+    const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits, A.vis_kbits);
     char *vlds = lds + (size_t)A.ef_cap * 8;
     if (A.counter == nullptr) {
         const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
@@ -865,7 +909,7 @@ hipError_t launch_convert(const float *src, void *dst, int64_t count, int storag
     return hipGetLastError();
 }
 
-int walk_lds_bytes(int ef_cap, int vis_bits) { return walk_lds_bytes_impl(ef_cap, vis_bits); }
+int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits) { return walk_lds_bytes_impl(ef_cap, vis_bits, vis_kbits); }
 int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
 
 // Host stubs of the kernels, by row layout and storage (for occupancy queries).
