@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the walk kernel from two rocprofv3 counter passes
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source and ef.
-TRAFFIC = {"kernel_sha256_prefix": "3f5a50161a83efc2", "ef": 256, "bytes_per_launch": 30.276e9}
+TRAFFIC = {"kernel_sha256_prefix": "11b39afd0a5d9e31", "ef": 256, "bytes_per_launch": 27.520e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
@@ -150,28 +150,32 @@ def timed(form, steps, warmup, wl, rate_khz):
                 n_p=float(st["n_p"].mean()), flags=int((st["flags"] != 0).sum()))
 
 
-def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000), seconds=0.5):
-    """Serving form: Poisson arrivals into the continuous-batching server."""
+def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000, 400_000), seconds=0.5,
+            max_queries=50_000):
+    """Serving form: Poisson arrivals into the continuous-batching server.
+    Arrival i carries query i mod 10,000; each rate runs for `seconds` or
+    `max_queries` arrivals, whichever is fewer."""
     ctx = uhnsw.Context(0)
     ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16)
     out = []
     pos_of = {int(q): i for i, q in enumerate(gt["qidx"])}
     for rate in rates:
-        n = min(wl.nq, int(rate * seconds))
+        n = min(max_queries, int(rate * seconds))
+        qi = np.arange(n) % wl.nq
         rng = np.random.Generator(np.random.PCG64(rate))
         arrival = np.cumsum(rng.exponential(1e6 / rate, n))
         srv = uhnsw.Server(ctx, k_max=10, ef_max=ef,
                            params=uhnsw.default_params(beam_width=2, visited_slots=1024))
         try:
-            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[:n], wl.p[:n], wl.k[:n],
+            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[qi], wl.p[qi], wl.k[qi],
                                                                     np.full(n, ef, np.int32), arrival)
             info = srv.info()
         finally:
             srv.stop()
         lat_ms = (t_done - t_sub) / 1e3
         span_s = (t_done.max() - arrival[0]) / 1e6
-        sel = [i for i in range(n) if i in pos_of]
-        rec = float(np.mean([len(set(ids[i, :10].tolist()) & set(gt["ids"][pos_of[i]].tolist())) / 10
+        sel = [i for i in range(n) if int(qi[i]) in pos_of]
+        rec = float(np.mean([len(set(ids[i, :10].tolist()) & set(gt["ids"][pos_of[int(qi[i])]].tolist())) / 10
                              for i in sel])) if sel else None
         r = dict(offered_qps=rate, queries=n, achieved_qps=round(n / span_s, 1),
                  p50_ms=round(float(np.percentile(lat_ms, 50)), 3), p99_ms=round(float(np.percentile(lat_ms, 99)), 3),
@@ -180,7 +184,7 @@ def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 20
         log("serving", json.dumps(r))
         out.append(r)
     ctx.close()
-    return dict(form="BF16 walk, beam 2, fused launches on 4 streams, continuous batching", ef=ef, k=10,
+    return dict(form="BF16 walk, beam 2, fused launches on 2 streams, continuous batching", ef=ef, k=10,
                 rates=out)
 
 

@@ -213,7 +213,7 @@ typedef struct {
     int32_t ef_max;           /* largest ef (<= EFMAX)                        */
     int32_t max_inflight;     /* query slots, 0 = resident-wave capacity      */
     int32_t max_batch;        /* queries per launch, 0 = capacity / streams   */
-    int32_t streams;          /* concurrent launches, 0 = 4 (<= 16)           */
+    int32_t streams;          /* concurrent launches, 0 = 2 (<= 16)           */
     int32_t reserved;
     int64_t hbm_budget;       /* bytes for per-stream buffers, 0 = no limit  */
     uhnsw_params params;      /* Algorithm 1 parameters; launches are fused   */

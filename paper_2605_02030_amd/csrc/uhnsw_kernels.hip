@@ -119,13 +119,13 @@ struct Elem<f16_t> {
 // keys[r] = delta(row ids[r], q) for r < nrows. All lanes must call. The
 // loads of up to RB row-steps are issued before any arithmetic so that a
 // whole neighbour list is in flight at once.
-template <int G, int NCH, typename T, bool L1>
+template <int G, int NCH, typename T, bool L1, int RBV>
 __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64_t pitch,
                                                const int32_t *ids, int nrows, const float (&qv)[NCH][4],
                                                float *keys) {
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
-    constexpr int RB = (64 / (NCH * V)) > 0 ? (64 / (NCH * V)) : 1;
+    constexpr int RB = (RBV * 4 / (NCH * V * (int)sizeof(T))) > 0 ? (RBV * 4 / (NCH * V * (int)sizeof(T))) : 1;
     using E = Elem<T>;
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
@@ -166,13 +166,13 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
     }
 }
 
-template <int G, int NCH, typename T>
+template <int G, int NCH, typename T, int RBV>
 __device__ __forceinline__ void base_dists(bool l1, const T *base, int64_t pitch, const int32_t *ids, int nrows,
                                            const float (&qv)[NCH][4], float *keys) {
     if (l1)
-        rows_base_dist<G, NCH, T, true>(base, pitch, ids, nrows, qv, keys);
+        rows_base_dist<G, NCH, T, true, RBV>(base, pitch, ids, nrows, qv, keys);
     else
-        rows_base_dist<G, NCH, T, false>(base, pitch, ids, nrows, qv, keys);
+        rows_base_dist<G, NCH, T, false, RBV>(base, pitch, ids, nrows, qv, keys);
 }
 
 // --------------------------------------------------- sorted-list insert
@@ -369,7 +369,7 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
            ef > A.ef_cap;
 }
 
-template <int G, int NCH, typename T>
+template <int G, int NCH, typename T, int RBV>
 __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
@@ -427,7 +427,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     int32_t cur = Gr.entry;
     if (lane == 0) L.Uid[0] = cur;
     wave_sync();
-    base_dists<G, NCH, T>(l1, base, pitch, L.Uid, 1, qv, L.Uk);
+    base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, 1, qv, L.Uk);
     wave_sync();
     float kcur = L.Uk[0];
     int n_b = 1;
@@ -439,7 +439,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
             const int cnt = popc64(ballot(nb >= 0));
             if (nb >= 0) L.Uid[lane] = nb;  // valid ids come first in each row
             wave_sync();
-            base_dists<G, NCH, T>(l1, base, pitch, L.Uid, cnt, qv, L.Uk);
+            base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, cnt, qv, L.Uk);
             wave_sync();
             n_b += cnt;
             float kb = lane < cnt ? L.Uk[lane] : INFINITY;
@@ -533,7 +533,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (nnew == 0) continue;
         if (fresh) L.Uid[lanes_below(fm)] = nb;
         wave_sync();
-        base_dists<G, NCH, T>(l1, base, pitch, L.Uid, nnew, qv, L.Uk);
+        base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, nnew, qv, L.Uk);
         wave_sync();
         n_b += nnew;
         int min_new, n_in;
@@ -570,23 +570,29 @@ __device__ __forceinline__ int fetch_query(int32_t *counter) {
     return __builtin_amdgcn_readfirstlane(__shfl(v, 0, kWave));
 }
 
-// 4 waves per SIMD: with a 1,024-slot visited cache LDS admits 16+ waves per
-// CU, and the extra resident waves hide more gather latency than the few
-// spilled registers cost.
+// Occupancy target (waves per SIMD) and VGPRs given to row data in flight.
+// FP32 rows: 4 waves with a whole 32-row neighbour list in flight (64 VGPRs);
+// 16-bit rows: 32 VGPRs (a whole list as well) and 5 waves for rows of up to
+// 256 dimensions, 4 for longer rows. Measured on the 1M x 128 workload, a
+// fifth FP32 wave or a sixth 16-bit wave costs more in spills than it gains.
+template <typename T, int G>
+constexpr int walk_waves_per_eu() { return sizeof(T) == 4 ? 4 : (G <= 16 ? 5 : 4); }
+template <typename T>
+constexpr int walk_rb_vgprs() { return sizeof(T) == 4 ? 64 : 32; }
 template <int G, int NCH, typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) walk_kernel(SearchArgs A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<T, G>(), 8))) walk_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
         const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (qi < A.nq) walk_one<G, NCH, T>(A, qi, lds);
+        if (qi < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>()>(A, qi, lds);
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
     int qi = fetch_query(A.counter);
     while ((int64_t)qi < A.nq) {
-        walk_one<G, NCH, T>(A, qi, lds);
+        walk_one<G, NCH, T, walk_rb_vgprs<T>()>(A, qi, lds);
         qi = fetch_query(A.counter);
     }
 }
@@ -786,13 +792,20 @@ __device__ __forceinline__ void verify_call(const SearchArgs &A, int64_t qi, cha
     verify_one<G, NCH>(A, qi, lds, nc, nullptr, Cl);
 }
 
-// Occupancy target of the fused kernel: 3 waves per SIMD (<= 168 VGPRs) with
-// FP32 rows in flight, 4 (<= 128) with packed 16-bit rows.
-template <typename T>
-constexpr int fused_waves_per_eu() { return sizeof(T) == 4 ? 3 : 4; }
+// Occupancy target of the fused kernel and VGPRs given to row data in flight.
+// Rows of up to 256 dimensions (G <= 16 lanes per row): 5 waves per SIMD
+// (<= 96 VGPRs) with 32 VGPRs of row data, for every storage type; the
+// verification state makes this kernel larger than the walk, and the extra
+// waves pay for the smaller row batches (measured on the 1M x 128 workload).
+// Longer rows (one row per 32 or 64 lanes) keep four rows in flight instead:
+// 3 waves with FP32 rows, 4 with 16-bit rows (measured at d = 960).
+template <typename T, int G>
+constexpr int fused_waves_per_eu() { return G <= 16 ? 5 : (sizeof(T) == 4 ? 3 : 4); }
+template <typename T, int G>
+constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32); }
 
 template <int G, int NCH, typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T>(), 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T, G>(), 8)))
 search_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
@@ -802,7 +815,7 @@ search_kernel(SearchArgs A) {
     if (A.counter == nullptr) {
         const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
         if (qi < A.nq) {
-            const int nc = walk_one<G, NCH, T>(A, qi, lds);
+            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>()>(A, qi, lds);
             wave_sync();
             verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         }
@@ -811,7 +824,7 @@ search_kernel(SearchArgs A) {
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        const int nc = walk_one<G, NCH, T>(A, qi, lds);
+        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>()>(A, qi, lds);
         wave_sync();
         verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         wave_sync();

@@ -245,10 +245,16 @@ void dispatcher(uhnsw_server *S) {
         any_busy = false;
         for (auto &l : S->lanes) any_busy |= l.busy;
         if (any_busy) {
-            // batches in flight: poll their events again shortly
-            lk.unlock();
-            std::this_thread::yield();
-            lk.lock();
+            // Batches in flight: check their events again after a short wait.
+            // The wait releases the lock, so submitters and pollers are not
+            // starved by this loop; a submit that finds an idle lane ends it.
+            S->cv.wait_for(lk, std::chrono::microseconds(20), [&] {
+                if (S->stop.load()) return true;
+                if (S->pending.empty()) return false;
+                for (auto &l : S->lanes)
+                    if (!l.busy) return true;
+                return false;
+            });
         } else {
             S->cv.wait(lk, [&] { return S->stop.load() || !S->pending.empty(); });
         }
@@ -284,7 +290,11 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
     S->cfg = *cfg;
     S->d = uhnsw::ctx_dim(ctx);
     S->device = uhnsw::ctx_device(ctx);
-    const int streams = cfg->streams ? cfg->streams : 4;
+    // Two lanes by default: one batch runs while the next one gathers
+    // arrivals. HIP gives a process four hardware queues by default and the
+    // context's own streams hold some of them; more lanes than free queues
+    // serialise behind each other and measured slower.
+    const int streams = cfg->streams ? cfg->streams : 2;
     // LDS budget: a query occupies one wave; admit at most as many queries
     // as the device holds resident waves (16 per CU unless told otherwise)
     const int wave_capacity = cus * 16;
