@@ -36,6 +36,10 @@ TRAFFIC = {"kernel_sha256_prefix": "11b39afd0a5d9e31", "ef": 256, "bytes_per_lau
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
+# workload -> n actually used: the serving form's 10M-row graphs are not built
+# here (about an hour of CPU per graph pair), a 1M-row index of the same
+# distribution stands in for it
+REDUCED_N = {5: 1_000_000}
 TARGET_RECALL = 0.9
 
 
@@ -151,12 +155,14 @@ def timed(form, steps, warmup, wl, rate_khz):
 
 
 def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000, 400_000), seconds=0.5,
-            max_queries=50_000):
+            max_queries=50_000, storage=None, k=None, k_max=10, label="BF16"):
     """Serving form: Poisson arrivals into the continuous-batching server.
-    Arrival i carries query i mod 10,000; each rate runs for `seconds` or
-    `max_queries` arrivals, whichever is fewer."""
+    Arrival i carries query i mod nq; each rate runs for `seconds` or
+    `max_queries` arrivals, whichever is fewer. `k` gives each query's K
+    (default: the workload's), `ef` one efSearch for all."""
     ctx = uhnsw.Context(0)
-    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16)
+    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16 if storage is None else storage)
+    kq = wl.k if k is None else k
     out = []
     pos_of = {int(q): i for i, q in enumerate(gt["qidx"])}
     for rate in rates:
@@ -164,10 +170,10 @@ def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 20
         qi = np.arange(n) % wl.nq
         rng = np.random.Generator(np.random.PCG64(rate))
         arrival = np.cumsum(rng.exponential(1e6 / rate, n))
-        srv = uhnsw.Server(ctx, k_max=10, ef_max=ef,
+        srv = uhnsw.Server(ctx, k_max=k_max, ef_max=ef,
                            params=uhnsw.default_params(beam_width=2, visited_slots=1024))
         try:
-            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[qi], wl.p[qi], wl.k[qi],
+            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[qi], wl.p[qi], kq[qi],
                                                                     np.full(n, ef, np.int32), arrival)
             info = srv.info()
         finally:
@@ -184,8 +190,8 @@ def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 20
         log("serving", json.dumps(r))
         out.append(r)
     ctx.close()
-    return dict(form="BF16 walk, beam 2, fused launches on 2 streams, continuous batching", ef=ef, k=10,
-                rates=out)
+    return dict(form=f"{label} walk, beam 2, fused launches on 2 streams, continuous batching", ef=ef,
+                k=sorted(set(int(x) for x in np.unique(kq))), rates=out)
 
 
 def cpu_baseline(wl, g1, g2, ef, budget_s=15.0):
@@ -221,8 +227,9 @@ def lp_dist64(base, q, ids, p):
 
 
 def run_secondary(a, torch, uhnsw, sg, synth):
-    """Workload 3 (precision form) or 4 (batching form): one JSON line."""
-    wl = synth.make_workload(a.workload)
+    """Workload 3 (precision form), 4 (batching form) or 5 (serving form, at
+    a tenth of its size): one JSON line."""
+    wl = synth.make_workload(a.workload, n=REDUCED_N.get(a.workload))
     log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq}")
     gt = gt_for(wl)
     g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
@@ -258,7 +265,26 @@ def run_secondary(a, torch, uhnsw, sg, synth):
             err = max(err, float(np.max(np.abs(dists_np[i, :kk] - d64) / d64)))
         return rec, err
 
-    if a.workload == 4:
+    if a.workload == 5:
+        # the same index in batch mode for reference: one fused persistent launch, FP16 walk
+        ef_t = torch.from_numpy(wl.ef).to(dev)
+        efmax = int(wl.ef.max())
+        ctx = uhnsw.Context(0)
+        ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_F16)
+        prm = ctx.autotune(q, p, k, ef_t, kmax, efmax, params=uhnsw.default_params(fused=1, persistent=1),
+                           allow_beam=True)
+        prm.graph = 1
+        dt = timed_run(ctx, ef_t, efmax, prm, a.steps)
+        rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
+        out["forms"]["fp16-batched"] = dict(qps=round(wl.nq / dt, 1), ms_per_launch=round(dt * 1e3, 3),
+                                            recall_at_10=round(rec, 4), max_rel_dist_err=err,
+                                            beam=prm.beam_width, slots=prm.visited_slots,
+                                            wpb=prm.waves_per_block, persistent=prm.persistent)
+        log("fp16-batched", json.dumps(out["forms"]["fp16-batched"]))
+        ctx.close()
+        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, efmax, storage=uhnsw.STORE_F16, k_max=kmax,
+                                 label="FP16")
+    elif a.workload == 4:
         ef_t = torch.from_numpy(wl.ef).to(dev)
         efmax = int(wl.ef.max())
         for name, batched in (("plain", False), ("batched", True)):
@@ -313,8 +339,9 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4),
-                    help="2: the headline workload; 3: precision form; 4: batching form")
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5),
+                    help="2: the headline workload; 3: precision form; 4: batching form; "
+                         "5: serving form (n = 1,000,000 of its 10,000,000)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()

@@ -123,6 +123,14 @@ def _gamma_feat(rng_pts, scales, n):
     return out
 
 
+def _size_name(n: int) -> str:
+    """10_000 -> '10k', 1_183_514 -> '1.18M' (three significant digits)."""
+    for div, suf in ((1_000_000, "M"), (1_000, "k")):
+        if n >= div:
+            return f"{float(f'{n / div:.3g}'):g}{suf}"
+    return str(n)
+
+
 def make_workload(cfg: int, n: int | None = None, nq: int | None = None,
                   d: int | None = None) -> Workload:
     """Build workload ``cfg`` (1..5). ``n``/``nq``/``d`` override the sizes
@@ -168,5 +176,8 @@ def make_workload(cfg: int, n: int | None = None, nq: int | None = None,
         ef = np.maximum(k, 128).astype(np.int32)
     else:
         raise ValueError(f"unknown workload {cfg}")
-    return Workload(cfg=cfg, name=spec["name"], base=base, queries=queries,
+    name = spec["name"]
+    if (n, d) != (spec["n"], spec["d"]):  # reduced case: name its own sizes
+        name = f"{name.split('-')[0]}-{_size_name(n)}-d{d}"
+    return Workload(cfg=cfg, name=name, base=base, queries=queries,
                     p=p, k=k, ef=ef, graph_seed=s0 + 5)

@@ -8,9 +8,11 @@ definition of the U-HNSW paper, Sec. 4.1.2) on the seeded inputs from
       coprime to the 16-value p grid, so each p appears 125 times;
   workload 3 (gammafeat-1M-d960): every 10th query (100 of 1,000);
   workload 4 (unitgauss-1.18M-d100): every 30th query starting at 1 (the
-      K = 10 queries; 334 of 10,000).
+      K = 10 queries; 334 of 10,000);
+  workload 5 at n = 1,000,000 (unitgauss-1M-d96, the serving form's shape
+      at a tenth of its size): every 10th query (200 of 2,000).
 
-    python tests/golden/make_groundtruth.py [--workload 2|3|4] [--threads N]
+    python tests/golden/make_groundtruth.py [--workload 2|3|4|5] [--threads N]
 """
 import argparse
 import os
@@ -26,7 +28,8 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLE = {2: (0, 5), 3: (0, 10), 4: (1, 30)}  # workload -> (first query, stride)
+SAMPLE = {2: (0, 5), 3: (0, 10), 4: (1, 30), 5: (0, 10)}  # workload -> (first query, stride)
+SIZE = {5: 1_000_000}  # workload -> reduced n
 K = 10
 
 
@@ -35,7 +38,7 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--workload", type=int, default=2, choices=sorted(SAMPLE))
     a = ap.parse_args()
-    wl = synth.make_workload(a.workload)
+    wl = synth.make_workload(a.workload, n=SIZE.get(a.workload))
     first, stride = SAMPLE[a.workload]
     qidx = np.arange(first, wl.nq, stride, dtype=np.int32)
     out = os.path.join(HERE, f"gt_{wl.name}.npz")
