@@ -162,8 +162,13 @@ int uhnsw_search(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *
  * this or the ranges above, or whose vector is not finite, is not searched:
  * its row is padded and its stats get UHNSW_QBAD. cand_ids / cand_keys (device, [nq x c_stride], may be
  * NULL) receive C and its base-metric keys (-1 / +inf padded). Buffers are
- * borrowed until the stream's work completes.
- * Errors: EINVAL (host-checkable arguments), ESTATE, ENOMEM, EDEVICE. */
+ * borrowed until the stream's work completes. Searches on different streams
+ * may run at the same time: each stream gets its own scratch (candidate
+ * lists, work counter, timing events, captured hipGraph) on first use, up to
+ * 64 streams per context. Calls on one context from several host threads at
+ * once are not supported.
+ * Errors: EINVAL (host-checkable arguments), ESTATE, ENOMEM, EDEVICE,
+ * EUNSUPPORTED (a 65th stream). */
 int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
                         const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm,
                         int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,

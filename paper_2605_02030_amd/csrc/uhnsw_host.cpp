@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -40,6 +41,9 @@ struct DevBuf {
     }
 };
 
+// streams one context serves at once (each holds its own search scratch)
+constexpr int kMaxStreams = 64;
+
 struct GraphKey {
     const void *ptrs[16];
     int64_t nq;
@@ -67,18 +71,25 @@ struct uhnsw_ctx {
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
     GraphDev g[2];
-    // per-search scratch
-    DevBuf cand_ids, cand_keys, ncand, stats, counter, mtab;
+    DevBuf mtab;
     double mtab_tau = -1.0;
+    // Per-launch-stream scratch: searches on different streams may run
+    // concurrently, so everything a search writes besides the caller's
+    // outputs (candidate lists, counts, default stats, the work counter,
+    // timing events, the captured hipGraph) belongs to its stream.
+    struct StreamSet {
+        hipStream_t stream = nullptr;
+        DevBuf cand_ids, cand_keys, ncand, stats, counter;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        bool timed = false;
+        hipGraphExec_t gexec = nullptr;
+        GraphKey gkey{};
+    };
+    std::vector<std::unique_ptr<StreamSet>> sets;
+    StreamSet *last_set = nullptr;  // the most recent search
     // staging for the host-pointer entry point
     DevBuf s_q, s_p, s_k, s_ef, s_ids, s_dists, s_stats;
-    // timing
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-    bool timed = false;
-    // hipGraph of the last captured launch sequence
-    hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    GraphKey gkey{};
+    hipStream_t cap_stream = nullptr;  // capture stream for hipGraphs
     int64_t graph_captures = 0;
     // host-pointer path under a hipGraph: pinned staging + the captured
     // sequence H2D copies -> kernels -> D2H copies
@@ -312,12 +323,6 @@ int uhnsw_create(int device, uhnsw_ctx **out) {
         delete c;
         return UHNSW_EDEVICE;
     }
-    for (auto &ev : c->ev)
-        if ((e = hipEventCreate(&ev)) != hipSuccess) {
-            g_create_error = std::string("hipEventCreate: ") + hipGetErrorString(e);
-            uhnsw_destroy(c);
-            return UHNSW_EDEVICE;
-        }
     *out = c;
     return UHNSW_OK;
 }
@@ -326,18 +331,23 @@ void uhnsw_destroy(uhnsw_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (auto &ev : c->ev)
-        if (ev) (void)hipEventDestroy(ev);
-    DevBuf *bufs[] = {&c->f32_base, &c->walk_base, &c->cand_ids, &c->cand_keys, &c->ncand, &c->stats,
-                      &c->counter, &c->mtab, &c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids, &c->s_dists,
-                      &c->s_stats};
+    for (auto &S : c->sets) {
+        if (S->stream) (void)hipStreamSynchronize(S->stream);
+        for (auto &ev : S->ev)
+            if (ev) (void)hipEventDestroy(ev);
+        DevBuf *sb[] = {&S->cand_ids, &S->cand_keys, &S->ncand, &S->stats, &S->counter};
+        for (DevBuf *b : sb) b->reset();
+        if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+    }
+    c->sets.clear();
+    DevBuf *bufs[] = {&c->f32_base, &c->walk_base, &c->mtab, &c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids,
+                      &c->s_dists, &c->s_stats};
     for (DevBuf *b : bufs) b->reset();
     for (auto &g : c->g) {
         g.adj0.reset();
         g.up_off.reset();
         g.up_adj.reset();
     }
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->hgexec) (void)hipGraphExecDestroy(c->hgexec);
     for (auto &h : c->hp)
         if (h.p) (void)hipHostFree(h.p);
@@ -418,18 +428,21 @@ int uhnsw_device_info(const uhnsw_ctx *c_, int32_t *num_cus, int32_t *wall_clock
 int uhnsw_last_timing(const uhnsw_ctx *c_, float *walk_ms, float *verify_ms) {
     uhnsw_ctx *c = const_cast<uhnsw_ctx *>(c_);
     if (!c || !walk_ms || !verify_ms) return UHNSW_EINVAL;
-    if (!c->timed) return fail(c, UHNSW_ESTATE, "no timed search yet");
-    HIP_OR_FAIL(c, hipEventSynchronize(c->ev[2]));
-    HIP_OR_FAIL(c, hipEventElapsedTime(walk_ms, c->ev[0], c->ev[1]));
-    HIP_OR_FAIL(c, hipEventElapsedTime(verify_ms, c->ev[1], c->ev[2]));
+    const auto *S = c->last_set;
+    if (!S || !S->timed) return fail(c, UHNSW_ESTATE, "no timed search yet");
+    HIP_OR_FAIL(c, hipEventSynchronize(S->ev[2]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(walk_ms, S->ev[0], S->ev[1]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(verify_ms, S->ev[1], S->ev[2]));
     return UHNSW_OK;
 }
 
-int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
-                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
-                        float *cand_keys, int32_t c_stride, void *stream) {
-    if (!c) return UHNSW_EINVAL;
+// One search enqueued on `stream` with the scratch set S (the set of the
+// stream the work finally runs on; under capture `stream` is the capture
+// stream).
+static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries, int64_t nq, const float *p,
+                     const int32_t *k, const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                     int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                     float *cand_keys, int32_t c_stride, void *stream) {
     if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
     if (nq < 0 || nq > INT32_MAX) return fail(c, UHNSW_EINVAL, "nq=%lld outside [0, 2^31)", (long long)nq);
@@ -496,8 +509,8 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     if (stats) {
         a.stats = stats;
     } else {
-        HIP_OR_FAIL(c, c->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
-        a.stats = c->stats.as<uhnsw_stats>();
+        HIP_OR_FAIL(c, S->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
+        a.stats = S->stats.as<uhnsw_stats>();
     }
     if (prm.fused) {
         a.cand_ids = cand_ids;  // C stays in LDS unless the caller asks for it
@@ -507,16 +520,16 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     } else {
         const int32_t cs = cand_ids ? c_stride : ef_max;
         if (!cand_ids) {
-            HIP_OR_FAIL(c, c->cand_ids.ensure((size_t)nq * cs * 4));
-            HIP_OR_FAIL(c, c->cand_keys.ensure((size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, S->cand_ids.ensure((size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, S->cand_keys.ensure((size_t)nq * cs * 4));
         }
-        HIP_OR_FAIL(c, c->ncand.ensure((size_t)nq * 4));
-        a.cand_ids = cand_ids ? cand_ids : c->cand_ids.as<int32_t>();
-        a.cand_keys = cand_ids ? cand_keys : c->cand_keys.as<float>();
+        HIP_OR_FAIL(c, S->ncand.ensure((size_t)nq * 4));
+        a.cand_ids = cand_ids ? cand_ids : S->cand_ids.as<int32_t>();
+        a.cand_keys = cand_ids ? cand_keys : S->cand_keys.as<float>();
         a.c_stride = cs;
-        a.ncand = c->ncand.as<int32_t>();
+        a.ncand = S->ncand.as<int32_t>();
     }
-    if (prm.persistent) HIP_OR_FAIL(c, c->counter.ensure(4));
+    if (prm.persistent) HIP_OR_FAIL(c, S->counter.ensure(4));
 
     // the kernels of one search, in stream order
     const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
@@ -544,29 +557,30 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
         hipError_t e = hipSuccess;
         SearchArgs b = a;
         if (prm.persistent) {
-            b.counter = c->counter.as<int32_t>();
+            b.counter = S->counter.as<int32_t>();
             if ((e = launch_fill_i32(b.counter, 0, 1, st)) != hipSuccess) return e;
         }
-        if (timed && (e = hipEventRecord(c->ev[0], st)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(S->ev[0], st)) != hipSuccess) return e;
         if (prm.fused) {
             b.lds_wave_bytes = pl.search_bytes;
             if ((e = launch_search(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
-            if (timed && (e = hipEventRecord(c->ev[1], st)) != hipSuccess) return e;
+            if (timed && (e = hipEventRecord(S->ev[1], st)) != hipSuccess) return e;
         } else {
             b.lds_wave_bytes = pl.walk_bytes;
             if ((e = launch_walk(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
-            if (timed && (e = hipEventRecord(c->ev[1], st)) != hipSuccess) return e;
+            if (timed && (e = hipEventRecord(S->ev[1], st)) != hipSuccess) return e;
             b.lds_wave_bytes = pl.verify_bytes;
             b.counter = nullptr;
             if ((e = launch_verify(b, c->layout, grid_all, st)) != hipSuccess) return e;
         }
-        if (timed && (e = hipEventRecord(c->ev[2], st)) != hipSuccess) return e;
+        if (timed && (e = hipEventRecord(S->ev[2], st)) != hipSuccess) return e;
         return hipSuccess;
     };
 
-    c->timed = prm.timing != 0;
+    S->timed = prm.timing != 0;
+    c->last_set = S;
     if (!prm.graph) {
-        HIP_OR_FAIL(c, enqueue(s, c->timed));
+        HIP_OR_FAIL(c, enqueue(s, S->timed));
         return UHNSW_OK;
     }
     // hipGraph: capture the launch sequence once per distinct argument set,
@@ -589,10 +603,10 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     key.prm = prm;
     key.prm.timing = 0;
     key.prm.graph = 0;
-    if (!c->gexec || std::memcmp(&key, &c->gkey, sizeof key) != 0) {
-        if (c->gexec) {
-            (void)hipGraphExecDestroy(c->gexec);
-            c->gexec = nullptr;
+    if (!S->gexec || std::memcmp(&key, &S->gkey, sizeof key) != 0) {
+        if (S->gexec) {
+            (void)hipGraphExecDestroy(S->gexec);
+            S->gexec = nullptr;
         }
         if (!c->cap_stream) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HIP_OR_FAIL(c, hipStreamSynchronize(s));
@@ -602,19 +616,49 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
         hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
         if (e != hipSuccess) return dev_fail(c, e, "enqueue under capture");
         if (e2 != hipSuccess) return dev_fail(c, e2, "hipStreamEndCapture");
-        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        e = hipGraphInstantiate(&S->gexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate");
-        c->gkey = key;
+        S->gkey = key;
         ++c->graph_captures;
     }
-    if (c->timed) HIP_OR_FAIL(c, hipEventRecord(c->ev[0], s));
-    HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, s));
-    if (c->timed) {
-        HIP_OR_FAIL(c, hipEventRecord(c->ev[1], s));
-        HIP_OR_FAIL(c, hipEventRecord(c->ev[2], s));
+    if (S->timed) HIP_OR_FAIL(c, hipEventRecord(S->ev[0], s));
+    HIP_OR_FAIL(c, hipGraphLaunch(S->gexec, s));
+    if (S->timed) {
+        HIP_OR_FAIL(c, hipEventRecord(S->ev[1], s));
+        HIP_OR_FAIL(c, hipEventRecord(S->ev[2], s));
     }
     return UHNSW_OK;
+}
+
+// The scratch set of a launch stream, created on first use.
+static int stream_set(uhnsw_ctx *c, hipStream_t st, uhnsw_ctx::StreamSet **out) {
+    for (auto &S : c->sets)
+        if (S->stream == st) {
+            *out = S.get();
+            return UHNSW_OK;
+        }
+    if (c->sets.size() >= (size_t)kMaxStreams)
+        return fail(c, UHNSW_EUNSUPPORTED, "searches on more than %d streams per context", kMaxStreams);
+    auto S = std::make_unique<uhnsw_ctx::StreamSet>();
+    S->stream = st;
+    for (auto &ev : S->ev) HIP_OR_FAIL(c, hipEventCreate(&ev));
+    *out = S.get();
+    c->sets.push_back(std::move(S));
+    return UHNSW_OK;
+}
+
+int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                        float *cand_keys, int32_t c_stride, void *stream) {
+    if (!c) return UHNSW_EINVAL;
+    if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
+    uhnsw_ctx::StreamSet *S = nullptr;
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    if (int r = stream_set(c, reinterpret_cast<hipStream_t>(stream), &S)) return r;
+    return search_on(c, S, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists, stats, cand_ids,
+                     cand_keys, c_stride, stream);
 }
 
 int uhnsw_graph_captures(const uhnsw_ctx *c, int64_t *count) {
@@ -731,6 +775,8 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     HIP_OR_FAIL(c, c->s_dists.ensure(nqs * k_stride * 4));
     HIP_OR_FAIL(c, c->s_stats.ensure(nqs * sizeof(uhnsw_stats)));
     hipStream_t s = c->stream;
+    uhnsw_ctx::StreamSet *S = nullptr;
+    if (int r = stream_set(c, s, &S)) return r;
     uhnsw_params prm;
     if (prm_in)
         prm = *prm_in;
@@ -742,9 +788,10 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     // the search through one set of host buffers: 4 copies in, kernels, 3 out
     auto enqueue = [&](hipStream_t st, void *const *host, const uhnsw_params &pr) -> int {
         for (int i = 0; i < 4; ++i) HIP_OR_FAIL(c, hipMemcpyAsync(dev[i], host[i], bytes[i], hipMemcpyHostToDevice, st));
-        int r = uhnsw_search_device(c, c->s_q.as<float>(), nq, c->s_p.as<float>(), c->s_k.as<int32_t>(),
-                                    c->s_ef.as<int32_t>(), k_max, ef_max, &pr, k_stride, c->s_ids.as<int64_t>(),
-                                    c->s_dists.as<float>(), c->s_stats.as<uhnsw_stats>(), nullptr, nullptr, 0, st);
+        // the scratch of c->stream, also while capturing: the graph runs there
+        int r = search_on(c, S, c->s_q.as<float>(), nq, c->s_p.as<float>(), c->s_k.as<int32_t>(),
+                          c->s_ef.as<int32_t>(), k_max, ef_max, &pr, k_stride, c->s_ids.as<int64_t>(),
+                          c->s_dists.as<float>(), c->s_stats.as<uhnsw_stats>(), nullptr, nullptr, 0, st);
         if (r) return r;
         for (int i = 4; i < 7; ++i) {
             if (i == 6 && !stats) break;

@@ -159,3 +159,35 @@ def test_host_path_graph_with_copies(torch_cuda, ctxb, wl1):
     d = ctxb.search(wl.queries[:37], p[:37], k[:37], ef[:37], params=prm_e, k_stride=100)
     np.testing.assert_array_equal(c[0], d[0])
     assert ctxb.graph_captures() == before + 2
+
+
+def test_concurrent_streams(torch_cuda, ctxb, wl1):
+    """Searches on two streams of one context at the same time (persistent,
+    hipGraph-replayed, each stream with its own scratch) equal the same
+    searches run one after another."""
+    from paper_2605_02030_amd import uhnsw
+
+    torch = torch_cuda
+    wl, _, _ = wl1
+    dev = torch.device("cuda:0")
+    p, k, ef = _mixed(wl, seed=36)
+    tq = torch.from_numpy(wl.queries).to(dev)
+    tp, tk, te = (torch.from_numpy(x).to(dev) for x in (p, k, ef))
+    halves = (slice(0, 50), slice(50, 100))
+    prm = uhnsw.default_params(fused=1, persistent=1, graph=1)
+    ref = [run_device(torch, ctxb, wl.queries[h], p[h], k[h], ef[h], 100, 256, params=prm) for h in halves]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [(torch.full((50, 100), -7, dtype=torch.int64, device=dev),
+             torch.full((50, 100), -7.0, dtype=torch.float32, device=dev),
+             torch.zeros((50, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)) for _ in halves]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for h, st, (ids, dists, stats) in zip(halves, streams, outs):
+            ctxb.search_device(tq[h], tp[h], tk[h], te[h], 100, 256, ids, dists, stats, params=prm, stream=st)
+        torch.cuda.synchronize()
+        for r, (ids, dists, stats) in zip(ref, outs):
+            np.testing.assert_array_equal(ids.cpu().numpy(), r[0])
+            np.testing.assert_array_equal(dists.cpu().numpy(), r[1])
+            st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(50)
+            np.testing.assert_array_equal(st["n_p"], r[2]["n_p"])
+            np.testing.assert_array_equal(st["n_exp"], r[2]["n_exp"])
