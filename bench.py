@@ -25,6 +25,11 @@ import time
 
 import numpy as np
 
+# Two batches in flight need their streams on different hardware queues; HIP
+# gives a process four by default and the library and torch hold some.
+# Must be set before HIP initialises.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -85,7 +90,8 @@ class Form:
         self.ef = self.torch.full((self.nq,), ef, dtype=torch_int32(self.torch), device="cuda:0")
         if self.persistent and ef not in self.tuned:
             base = self.uhnsw.default_params(fused=1, persistent=1, graph=1)
-            t = self.ctx.autotune(self.q, self.p, self.k, self.ef, 10, ef, params=base, allow_beam=True)
+            t = self.ctx.autotune(self.q, self.p, self.k, self.ef, 10, ef, params=base, allow_beam=True,
+                                  pipelined=self.pipeline > 1, stream=self.streams[0])
             t.graph = 1
             self.tuned[ef] = t
             log(f"{self.name} ef={ef}: autotuned beam={t.beam_width} slots={t.visited_slots} "
@@ -265,13 +271,21 @@ def run_secondary(a, torch, uhnsw, sg, synth):
     stats = torch.zeros((wl.nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
     out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries": wl.nq, "forms": {}}
 
-    def timed_run(ctx, ef_t, efmax, prm, steps):
-        for _ in range(2):
-            ctx.search_device(q, p, k, ef_t, kmax, efmax, ids, dists, stats, params=prm)
+    spare = (torch.empty_like(ids), torch.empty_like(dists), torch.empty_like(stats))
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+
+    def timed_run(ctx, ef_t, efmax, prm, steps, pipeline=1):
+        """Seconds per launch; with pipeline=2 consecutive launches alternate
+        between two streams and output sets (the last one lands in ids)."""
+        sets = ((ids, dists, stats), spare)
+        for i in range(2):
+            o = sets[i % pipeline]
+            ctx.search_device(q, p, k, ef_t, kmax, efmax, *o, params=prm, stream=streams[i % pipeline])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
-            ctx.search_device(q, p, k, ef_t, kmax, efmax, ids, dists, stats, params=prm)
+        for i in range(steps):
+            j = (i + 1 - steps) % pipeline  # the last launch uses the first set
+            ctx.search_device(q, p, k, ef_t, kmax, efmax, *sets[j], params=prm, stream=streams[j])
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
@@ -309,19 +323,20 @@ def run_secondary(a, torch, uhnsw, sg, synth):
     elif a.workload == 4:
         ef_t = torch.from_numpy(wl.ef).to(dev)
         efmax = int(wl.ef.max())
-        for name, batched in (("plain", False), ("batched", True)):
+        for name, batched, pipe in (("plain", False, 1), ("batched", True, 1), ("batched-2-streams", True, 2)):
             ctx = uhnsw.Context(0)
             ctx.load_graphs(wl.base, g1, g2)
             if batched:
                 prm = ctx.autotune(q, p, k, ef_t, kmax, efmax,
-                                   params=uhnsw.default_params(fused=1, persistent=1), allow_beam=True)
+                                   params=uhnsw.default_params(fused=1, persistent=1), allow_beam=True,
+                                   pipelined=pipe > 1, stream=streams[0])
                 prm.graph = 1
                 knobs = dict(beam=prm.beam_width, slots=prm.visited_slots, wpb=prm.waves_per_block,
                              persistent=prm.persistent)
             else:
                 prm = uhnsw.default_params()
                 knobs = {}
-            dt = timed_run(ctx, ef_t, efmax, prm, a.steps)
+            dt = timed_run(ctx, ef_t, efmax, prm, a.steps, pipeline=pipe)
             rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
             st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(wl.nq)
             lat = ((st["t_end"].astype(np.int64) - st["t_begin"].astype(np.int64).min()) % (1 << 32)) / \
@@ -404,11 +419,17 @@ def main():
     forms = {}
     specs = {"fp32": (uhnsw.STORE_F32, 0, 4), "bf16-batched": (uhnsw.STORE_BF16, 1, 2)}
     chosen_fp32 = None
+    probes = None
     for name in [f.strip() for f in a.forms.split(",") if f.strip()]:
         storage, persistent, elem = specs[name]
         f = Form(torch, uhnsw, wl, g1, g2, storage, persistent, name)
         f.row_bytes_per_elem = elem
         num_cus, rate_khz = f.ctx.device_info()
+        if name == "fp32":  # ceiling probes on the resident FP32 rows (512 B per row)
+            probes = dict(gather_512B_gbs=round(f.ctx.probe_gather(512), 1),
+                          gather_256B_gbs=round(f.ctx.probe_gather(256), 1),
+                          exp_log_lane_ops_per_s=float(f"{f.ctx.probe_transcendental():.4g}"))
+            log("probes", json.dumps(probes))
         if a.ef:
             f.set_ef(a.ef)
             ef, table = a.ef, []
@@ -465,6 +486,7 @@ def main():
                      "traffic": (TRAFFIC["bytes_per_launch"] if kernel_hash == TRAFFIC["kernel_sha256_prefix"]
                                  and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" else None),
                      "kernel": "walk_kernel", "walk_ms": m["walk_ms"]},
+        "probes": probes,
         "forms": forms,
     }
     if not a.no_serving:

@@ -177,12 +177,19 @@ int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const 
 /* Batching form: pick execution knobs for this index and query mix by
  * timing the search on the given device queries (same arrays and limits as
  * uhnsw_search_device): visited-cache slots, waves per block, persistent or
- * not, and -- only when allow_beam is set, since it changes the walk's
- * trajectory -- the beam width. Every other knob leaves results unchanged.
- * *prm is read for Algorithm 1's parameters and receives the chosen knobs.
- * Results are cached per (n, d, storage, ef range, k_max) in the context. */
+ * not, and -- only with UHNSW_TUNE_BEAM in `flags`, since it changes the
+ * walk's trajectory -- the beam width. Every other knob leaves results
+ * unchanged. With UHNSW_TUNE_PIPELINED the knobs are timed as back-to-back
+ * launches alternating between `stream` and a second stream of the
+ * context (the throughput of a caller that keeps two batches in flight)
+ * instead of one launch at a time. *prm is read for Algorithm 1's
+ * parameters and receives the chosen knobs. Results are cached per (n, d,
+ * storage, ef range, k_max, flags, fused) in the context.
+ * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
+#define UHNSW_TUNE_BEAM 1
+#define UHNSW_TUNE_PIPELINED 2
 int uhnsw_autotune(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t allow_beam, uhnsw_params *prm,
+                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t flags, uhnsw_params *prm,
                    void *stream);
 
 /* Number of hipGraph captures made so far (prm->graph); replays do not
@@ -192,6 +199,22 @@ int uhnsw_graph_captures(const uhnsw_ctx *ctx, int64_t *count);
 /* Lane layout of the walk's FP32 base distance for the loaded index:
  * element j is summed by lane (j / v) mod g, lanes combine pairwise. */
 int uhnsw_get_layout(const uhnsw_ctx *ctx, int32_t *g, int32_t *v);
+
+/* Ceiling probes for reading the rooflines (measurement only, not part of
+ * the query path; synchronous on the context's stream).
+ * uhnsw_probe_gather: HBM rate, in GB/s (1e9 B/s), of random gathers of
+ * `row_bytes` (128, 256 or 512) from the loaded FP32 rows with the walk's
+ * access pattern (8 lanes per row, 16-B loads, 32 rows in flight per wave)
+ * but no dependency between batches: the rate the walk's gathers could
+ * reach at best. Row ids come from a fixed hash.
+ * Errors: EINVAL (NULL, row_bytes not 128/256/512 or above the row pitch),
+ * ESTATE (no index), ENOMEM, EDEVICE. */
+int uhnsw_probe_gather(uhnsw_ctx *ctx, int32_t row_bytes, double *gbs);
+
+/* uhnsw_probe_transcendental: v_exp_f32 + v_log_f32 lane operations per
+ * second over independent chains on every CU (the unit the verification's
+ * general-p power uses). Errors: EINVAL (NULL), ENOMEM, EDEVICE. */
+int uhnsw_probe_transcendental(uhnsw_ctx *ctx, double *ops_per_s);
 
 /* Device facts for callers that interpret uhnsw_stats: compute units and the
  * rate (kHz) of the wall clock behind t_begin / t_end. */

@@ -27,6 +27,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(bdir, exist_ok=True)
     jobs = []
     for src, flags, lang in (("uhnsw_kernels.hip", DEVICE_FLAGS, ["-x", "hip"]),
+                             ("uhnsw_probe.hip", DEVICE_FLAGS, ["-x", "hip"]),
                              ("uhnsw_host.cpp", HOST_FLAGS, ["-D__HIP_PLATFORM_AMD__"]),
                              ("uhnsw_serve.cpp", HOST_FLAGS, ["-D__HIP_PLATFORM_AMD__", "-pthread"])):
         obj = os.path.join(bdir, src + ".o")

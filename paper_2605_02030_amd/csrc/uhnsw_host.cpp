@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -89,7 +90,8 @@ struct uhnsw_ctx {
     StreamSet *last_set = nullptr;  // the most recent search
     // staging for the host-pointer entry point
     DevBuf s_q, s_p, s_k, s_ef, s_ids, s_dists, s_stats;
-    hipStream_t cap_stream = nullptr;  // capture stream for hipGraphs
+    hipStream_t cap_stream = nullptr;   // capture stream for hipGraphs
+    hipStream_t tune_stream = nullptr;  // second stream of the pipelined autotuner
     int64_t graph_captures = 0;
     // host-pointer path under a hipGraph: pinned staging + the captured
     // sequence H2D copies -> kernels -> D2H copies
@@ -330,9 +332,10 @@ int uhnsw_create(int device, uhnsw_ctx **out) {
 void uhnsw_destroy(uhnsw_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    // Wait for every search of this context: the caller's streams may already
+    // be gone, so the device is synchronised rather than each stream.
+    (void)hipDeviceSynchronize();
     for (auto &S : c->sets) {
-        if (S->stream) (void)hipStreamSynchronize(S->stream);
         for (auto &ev : S->ev)
             if (ev) (void)hipEventDestroy(ev);
         DevBuf *sb[] = {&S->cand_ids, &S->cand_keys, &S->ncand, &S->stats, &S->counter};
@@ -352,6 +355,7 @@ void uhnsw_destroy(uhnsw_ctx *c) {
     for (auto &h : c->hp)
         if (h.p) (void)hipHostFree(h.p);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->tune_stream) (void)hipStreamDestroy(c->tune_stream);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -661,6 +665,73 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
                      cand_keys, c_stride, stream);
 }
 
+int uhnsw_probe_gather(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {
+    if (!c || !gbs) return UHNSW_EINVAL;
+    if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
+    if (row_bytes != 128 && row_bytes != 256 && row_bytes != 512)
+        return fail(c, UHNSW_EINVAL, "row_bytes=%d not 128, 256 or 512", row_bytes);
+    if ((int64_t)row_bytes > c->pitch * 4)
+        return fail(c, UHNSW_EINVAL, "row_bytes=%d above the row pitch (%lld B)", row_bytes,
+                    (long long)(c->pitch * 4));
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    DevBuf sink;
+    HIP_OR_FAIL(c, sink.ensure(4));
+    const int blocks = c->num_cus * 8;  // 32 waves per CU requested, the hardware keeps what fits
+    const int iters = 256;
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(c, hipEventCreate(&e0));
+    HIP_OR_FAIL(c, hipEventCreate(&e1));
+    hipError_t e = launch_gather_probe(c->f32_base.as<float>(), c->n, c->pitch, row_bytes, blocks, iters, 1u,
+                                       sink.as<float>(), c->stream);  // warm-up
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float ms = 0;
+        if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+        if ((e = launch_gather_probe(c->f32_base.as<float>(), c->n, c->pitch, row_bytes, blocks, iters,
+                                     2u + (uint32_t)rep, sink.as<float>(), c->stream)) != hipSuccess)
+            break;
+        if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(c, e, "gather probe");
+    const double bytes = (double)blocks * 4 * iters * 32 * row_bytes;
+    *gbs = bytes / (best * 1e-3) / 1e9;
+    return UHNSW_OK;
+}
+
+int uhnsw_probe_transcendental(uhnsw_ctx *c, double *ops_per_s) {
+    if (!c || !ops_per_s) return UHNSW_EINVAL;
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    DevBuf sink;
+    HIP_OR_FAIL(c, sink.ensure(4));
+    const int blocks = c->num_cus * 8;
+    const int iters = 256;
+    hipEvent_t e0, e1;
+    HIP_OR_FAIL(c, hipEventCreate(&e0));
+    HIP_OR_FAIL(c, hipEventCreate(&e1));
+    hipError_t e = launch_trans_probe(blocks, iters, sink.as<float>(), c->stream);
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float ms = 0;
+        if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) break;
+        if ((e = launch_trans_probe(blocks, iters, sink.as<float>(), c->stream)) != hipSuccess) break;
+        if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return dev_fail(c, e, "transcendental probe");
+    const double ops = (double)blocks * 256 * iters * 8 * 2;  // one v_log and one v_exp per chain step
+    *ops_per_s = ops / (best * 1e-3);
+    return UHNSW_OK;
+}
+
 int uhnsw_graph_captures(const uhnsw_ctx *c, int64_t *count) {
     if (!c || !count) return UHNSW_EINVAL;
     *count = c->graph_captures;
@@ -668,15 +739,17 @@ int uhnsw_graph_captures(const uhnsw_ctx *c, int64_t *count) {
 }
 
 int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t allow_beam, uhnsw_params *prm,
+                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t flags, uhnsw_params *prm,
                    void *stream) {
     if (!c || !prm) return UHNSW_EINVAL;
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
     if (nq < 1) return fail(c, UHNSW_EINVAL, "autotune needs queries");
     const uint64_t key = ((uint64_t)c->n << 20) ^ ((uint64_t)c->d << 8) ^ ((uint64_t)c->storage << 4) ^
                          ((uint64_t)(ef_max <= 64 ? 0 : ef_max <= 128 ? 1 : ef_max <= 256 ? 2 : 3) << 40) ^
-                         ((uint64_t)k_max << 44) ^ ((uint64_t)(allow_beam != 0) << 60) ^
+                         ((uint64_t)k_max << 44) ^ ((uint64_t)(flags & 3) << 58) ^
                          ((uint64_t)(prm->fused != 0) << 61);
+    const bool allow_beam = (flags & UHNSW_TUNE_BEAM) != 0;
+    const bool pipelined = (flags & UHNSW_TUNE_PIPELINED) != 0;
     for (auto &e : c->tuned)
         if (e.first == key) {
             uhnsw_params t = e.second;
@@ -691,10 +764,17 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
             return UHNSW_OK;
         }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    DevBuf oid, od, os;
-    HIP_OR_FAIL(c, oid.ensure((size_t)nq * k_max * 8));
-    HIP_OR_FAIL(c, od.ensure((size_t)nq * k_max * 4));
-    HIP_OR_FAIL(c, os.ensure((size_t)nq * sizeof(uhnsw_stats)));
+    DevBuf oid[2], od[2], os[2];
+    for (int j = 0; j < (pipelined ? 2 : 1); ++j) {
+        HIP_OR_FAIL(c, oid[j].ensure((size_t)nq * k_max * 8));
+        HIP_OR_FAIL(c, od[j].ensure((size_t)nq * k_max * 4));
+        HIP_OR_FAIL(c, os[j].ensure((size_t)nq * sizeof(uhnsw_stats)));
+    }
+    // the second stream of the pipelined timing: the context's own stream
+    // unless the caller's is that one
+    if (pipelined && s == c->stream && !c->tune_stream)
+        HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->tune_stream, hipStreamNonBlocking));
+    hipStream_t st2[2] = {s, s == c->stream ? c->tune_stream : c->stream};
     uhnsw_params best = *prm;
     float best_ms = 1e30f;
     const int slots_c[] = {512, 1024, 2048, 4096};
@@ -714,8 +794,31 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
                     float ms[3];
                     bool ok = true;
                     for (int rep = -1; rep < 3 && ok; ++rep) {
+                        if (pipelined) {  // 4 launches, two in flight: wall time per launch
+                            t.timing = 0;
+                            if (rep >= 0) HIP_OR_FAIL(c, hipStreamSynchronize(s));
+                            const auto t0 = std::chrono::steady_clock::now();
+                            for (int l = 0; l < 4 && ok; ++l) {
+                                const int j = l & 1;
+                                int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
+                                                             oid[j].as<int64_t>(), od[j].as<float>(),
+                                                             os[j].as<uhnsw_stats>(), nullptr, nullptr, 0, st2[j]);
+                                if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
+                                    ok = false;
+                                    c->err.clear();
+                                } else if (rc) {
+                                    return rc;
+                                }
+                            }
+                            HIP_OR_FAIL(c, hipStreamSynchronize(st2[0]));
+                            HIP_OR_FAIL(c, hipStreamSynchronize(st2[1]));
+                            const double dt = std::chrono::duration<double, std::milli>(
+                                                  std::chrono::steady_clock::now() - t0).count();
+                            if (rep >= 0) ms[rep] = (float)(dt / 4);
+                            continue;
+                        }
                         int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
-                                                     oid.as<int64_t>(), od.as<float>(), os.as<uhnsw_stats>(),
+                                                     oid[0].as<int64_t>(), od[0].as<float>(), os[0].as<uhnsw_stats>(),
                                                      nullptr, nullptr, 0, s);
                         if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
                             ok = false;  // this shape does not fit: skip it

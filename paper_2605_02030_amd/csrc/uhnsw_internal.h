@@ -79,6 +79,12 @@ hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s)
 hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
+// ceiling probes (measurement only): `blocks` x 4 waves; a gather wave reads
+// iters x 32 random rows of row_bytes (128, 256 or 512) from rows of `pitch`
+// floats; a transcendental thread runs iters x 8 exp/log pairs
+hipError_t launch_gather_probe(const float *base, int64_t n, int64_t pitch, int row_bytes, int blocks, int iters,
+                               uint32_t seed, float *sink, hipStream_t s);
+hipError_t launch_trans_probe(int blocks, int iters, float *sink, hipStream_t s);
 hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
 int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits);
 int verify_lds_bytes(int kv_cap);

@@ -18,11 +18,13 @@ UHNSW_ESTATE, UHNSW_EIO, UHNSW_EBUSY, UHNSW_EUNSUPPORTED = -4, -5, -6, -7
 UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 1024, 1024
 STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
+UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
 
 EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
-           "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop")
+           "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
+           "uhnsw_probe_gather", "uhnsw_probe_transcendental")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -99,6 +101,9 @@ uhnsw_serve_stop = _sig("uhnsw_serve_stop", ctypes.c_int, [_P])
 uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
                          [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
+uhnsw_probe_gather = _sig("uhnsw_probe_gather", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_double)])
+uhnsw_probe_transcendental = _sig("uhnsw_probe_transcendental", ctypes.c_int,
+                                  [_P, ctypes.POINTER(ctypes.c_double)])
 
 
 class UhnswError(RuntimeError):
@@ -154,9 +159,9 @@ class Context:
         self.h = h
         self.n = self.d = 0
 
-    def close(self):
+    def close(self, _destroy=uhnsw_destroy):  # bound early: usable during interpreter shutdown
         if getattr(self, "h", None):
-            uhnsw_destroy(self.h)
+            _destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -227,16 +232,21 @@ class Context:
             cand_keys.data_ptr() if cand_keys is not None else None, cs, stream))
 
     def autotune(self, queries, p, k, ef, k_max: int, ef_max: int, params: uhnsw_params | None = None,
-                 allow_beam: bool = False, stream=None) -> uhnsw_params:
-        """Time the execution knobs on these device tensors; returns tuned params."""
+                 allow_beam: bool = False, pipelined: bool = False, stream=None) -> uhnsw_params:
+        """Time the execution knobs on these device tensors; returns tuned params.
+        allow_beam: also choose the beam width (changes the walk); pipelined:
+        time back-to-back launches with two in flight."""
         import torch
 
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        flags = (UHNSW_TUNE_BEAM if allow_beam else 0) | (UHNSW_TUNE_PIPELINED if pipelined else 0)
         prm = params if params is not None else default_params()
         prm = uhnsw_params.from_buffer_copy(prm)
         self._check(uhnsw_autotune(self.h, queries.data_ptr(), queries.shape[0], p.data_ptr(), k.data_ptr(),
-                                   ef.data_ptr(), int(k_max), int(ef_max), int(allow_beam), ctypes.byref(prm),
+                                   ef.data_ptr(), int(k_max), int(ef_max), flags, ctypes.byref(prm),
                                    stream))
         return prm
 
@@ -249,6 +259,18 @@ class Context:
         cus, khz = _I32(), _I32()
         self._check(uhnsw_device_info(self.h, ctypes.byref(cus), ctypes.byref(khz)))
         return cus.value, khz.value
+
+    def probe_gather(self, row_bytes: int) -> float:
+        """GB/s of random row gathers with the walk's access pattern (ceiling probe)."""
+        v = ctypes.c_double()
+        self._check(uhnsw_probe_gather(self.h, int(row_bytes), ctypes.byref(v)))
+        return v.value
+
+    def probe_transcendental(self) -> float:
+        """v_exp + v_log lane operations per second (ceiling probe)."""
+        v = ctypes.c_double()
+        self._check(uhnsw_probe_transcendental(self.h, ctypes.byref(v)))
+        return v.value
 
     def last_timing(self):
         w, v = ctypes.c_float(), ctypes.c_float()

@@ -133,6 +133,13 @@ def test_autotune_result_invariant(torch_cuda, ctxb, wl1):
     again = ctxb.autotune(tq, tp, tk, te, 100, 256, params=uhnsw.default_params(fused=1))
     assert (again.visited_slots, again.waves_per_block, again.persistent) == \
         (tuned.visited_slots, tuned.waves_per_block, tuned.persistent)  # cached
+    # timed as two launches in flight on two streams: knobs may differ, results may not
+    piped = ctxb.autotune(tq, tp, tk, te, 100, 256, params=uhnsw.default_params(fused=1), pipelined=True,
+                          stream=torch.cuda.Stream())
+    _say("autotuned (pipelined)", piped.visited_slots, piped.waves_per_block, piped.persistent, piped.beam_width)
+    assert piped.beam_width == 1 and piped.fused == 1
+    c = run_device(torch, ctxb, wl.queries, p, k, ef, 100, 256, params=piped)
+    _same(a, c)
 
 
 def test_host_path_graph_with_copies(torch_cuda, ctxb, wl1):
