@@ -541,7 +541,8 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     if (prm.persistent) {
         int per_cu = 0;
         const void *kp =
-            prm.fused ? search_kernel_ptr(c->layout, c->storage) : walk_kernel_ptr(c->layout, c->storage);
+            prm.fused ? search_kernel_ptr(c->layout, c->storage, prm.beam_width)
+                      : walk_kernel_ptr(c->layout, c->storage);
         const size_t lds_block = (size_t)(prm.fused ? pl.search_bytes : pl.walk_bytes) * pl.wpb;
         bool found = false;
         for (auto &o : c->occ)

@@ -90,7 +90,7 @@ int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits);
 int verify_lds_bytes(int kv_cap);
 const void *walk_kernel_ptr(int layout, int storage);
 const void *verify_kernel_ptr(int layout);
-const void *search_kernel_ptr(int layout, int storage);
+const void *search_kernel_ptr(int layout, int storage, int beam);
 int ctx_dim(const uhnsw_ctx *c);
 int ctx_device(const uhnsw_ctx *c);
 

@@ -183,15 +183,39 @@ __device__ __forceinline__ void base_dists(bool l1, const T *base, int64_t pitch
 // smallest position any new entry took (cap if none); *n_in the number of
 // new entries now in L. With dedupe_u, an id listed twice in U is kept once
 // (U holds at most kUCap entries then).
+// WIDE selects the walk's form: a four-way search and a rank loop that issues
+// its reads ahead, worth their extra registers on W's up to 1,024 entries;
+// verification's short lists use plain halving.
+template <bool WIDE>
 __device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const float *Uk, const int32_t *Ui,
                                  int nU, int32_t *Ulo, int32_t *Urank, int32_t *Slo, bool dedupe_u, int *min_new,
                                  int *n_in) {
     const int lane = lane_id();
     // 1. insertion point of each candidate; -1 marks a duplicate
+    // (lower bound by a four-way search: three pivots read together per step,
+    // so the dependent LDS round trips are about half those of halving)
     for (int u = lane; u < nU; u += kWave) {
         const float uk = Uk[u];
         const uint32_t ui = (uint32_t)Ui[u];
         int lo = 0, hi = nL;
+        while (WIDE && hi - lo >= 4) {
+            const int q = (hi - lo) >> 2;
+            const int m1 = lo + q, m2 = lo + 2 * q, m3 = lo + 3 * q;
+            const float k1 = Lk[m1], k2 = Lk[m2], k3 = Lk[m3];
+            const uint32_t i1 = Li[m1] & kIdMask, i2 = Li[m2] & kIdMask, i3 = Li[m3] & kIdMask;
+            const bool c1 = key_less(k1, i1, uk, ui), c2 = key_less(k2, i2, uk, ui), c3 = key_less(k3, i3, uk, ui);
+            if (c3) {
+                lo = m3 + 1;
+            } else if (c2) {
+                lo = m2 + 1;
+                hi = m3;
+            } else if (c1) {
+                lo = m1 + 1;
+                hi = m2;
+            } else {
+                hi = m1;
+            }
+        }
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
             if (key_less(Lk[mid], Li[mid] & kIdMask, uk, ui))
@@ -227,8 +251,20 @@ __device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const
             const float uk = Uk[u];
             const uint32_t ui = (uint32_t)Ui[u];
             rank = 0;
-            for (int j = 0; j < nU; ++j)
-                if (Ulo[j] >= 0 && key_less(Uk[j], (uint32_t)Ui[j], uk, ui)) ++rank;
+            if (WIDE) {
+                // all three reads of an entry issued together, four entries
+                // per step; no read waits on another entry's test
+#pragma unroll 4
+                for (int j = 0; j < nU; ++j) {
+                    const int lj = Ulo[j];
+                    const float kj = Uk[j];
+                    const uint32_t ij = (uint32_t)Ui[j];
+                    rank += ((lj >= 0) & ((kj < uk) | ((kj == uk) & (ij < ui)))) ? 1 : 0;
+                }
+            } else {
+                for (int j = 0; j < nU; ++j)
+                    if (Ulo[j] >= 0 && key_less(Uk[j], (uint32_t)Ui[j], uk, ui)) ++rank;
+            }
         }
         if (u < nU) Urank[u] = rank;
         nkeep += popc64(ballot(kept));
@@ -369,7 +405,7 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
            ef > A.ef_cap;
 }
 
-template <int G, int NCH, typename T, int RBV>
+template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER>
 __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
@@ -536,8 +572,31 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, nnew, qv, L.Uk);
         wave_sync();
         n_b += nnew;
+        // With W full, a new entry not below W's last one cannot enter: keep
+        // the others, compacted in their order. Late in the walk most
+        // expansions end here with nothing to merge.
+        int nu = nnew;
+        if ((FILTER == 2 || (FILTER == 1 && npick > 1)) && nW == ef) {
+            const float wk = L.Wk[nW - 1];
+            const uint32_t wi = L.Wi[nW - 1] & kIdMask;
+            const float k = lane < nnew ? L.Uk[lane] : 0.0f;
+            const int32_t id = lane < nnew ? L.Uid[lane] : 0;
+            const bool keep = lane < nnew && key_less(k, (uint32_t)id, wk, wi);
+            const uint64_t km = ballot(keep);
+            nu = popc64(km);
+            if (nu == 0) continue;
+            if (nu < nnew) {
+                wave_sync();
+                if (keep) {
+                    const int dst = lanes_below(km);
+                    L.Uk[dst] = k;
+                    L.Uid[dst] = id;
+                }
+                wave_sync();
+            }
+        }
         int min_new, n_in;
-        nW = merge_into_sorted(L.Wk, L.Wi, nW, ef, L.Uk, L.Uid, nnew, L.Ulo, L.Urank, L.Slo, npick > 1, &min_new,
+        nW = merge_into_sorted<WIDE>(L.Wk, L.Wi, nW, ef, L.Uk, L.Uid, nu, L.Ulo, L.Urank, L.Slo, npick > 1, &min_new,
                                &n_in);
         if (min_new < lb) lb = min_new;
     }
@@ -586,13 +645,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_w
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
         const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (qi < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>()>(A, qi, lds);
+        if (qi < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, qi, lds);
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
     int qi = fetch_query(A.counter);
     while ((int64_t)qi < A.nq) {
-        walk_one<G, NCH, T, walk_rb_vgprs<T>()>(A, qi, lds);
+        walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, qi, lds);
         qi = fetch_query(A.counter);
     }
 }
@@ -738,7 +797,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, c
     lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nR, qv, p, 0.0f, false, L.Bk);
     wave_sync();
     int dummy_min, dummy_in;
-    int nr = merge_into_sorted(L.Rk, L.Ri, 0, K, L.Bk, L.Bi, nR, L.Ulo, L.Urank, L.Slo, false, &dummy_min,
+    int nr = merge_into_sorted<false>(L.Rk, L.Ri, 0, K, L.Bk, L.Bi, nR, L.Ulo, L.Urank, L.Slo, false, &dummy_min,
                                &dummy_in);
     int pos = nR, batches = 0;
     while (pos < nc) {
@@ -751,7 +810,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, c
         wave_sync();
         // entries at +inf were aborted: move them out of the merge by id order
         int n_in = 0, min_new;
-        nr = merge_into_sorted(L.Rk, L.Ri, nr, K, L.Bk, L.Bi, nb, L.Ulo, L.Urank, L.Slo, false, &min_new, &n_in);
+        nr = merge_into_sorted<false>(L.Rk, L.Ri, nr, K, L.Bk, L.Bi, nb, L.Ulo, L.Urank, L.Slo, false, &min_new, &n_in);
         pos += nb;
         ++batches;
         if (nr - n_in >= m) break;
@@ -804,7 +863,10 @@ constexpr int fused_waves_per_eu() { return G <= 16 ? 5 : (sizeof(T) == 4 ? 3 : 
 template <typename T, int G>
 constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32); }
 
-template <int G, int NCH, typename T>
+// BEAM (1 or 2, equal to A.beam) specialises the fused kernel: with two
+// nodes per step the walk drops new entries that cannot enter a full W before
+// merging; with one the same test measured slower in this larger kernel.
+template <int G, int NCH, typename T, int BEAM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T, G>(), 8)))
 search_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
@@ -815,7 +877,7 @@ search_kernel(SearchArgs A) {
     if (A.counter == nullptr) {
         const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
         if (qi < A.nq) {
-            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>()>(A, qi, lds);
+            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0>(A, qi, lds);
             wave_sync();
             verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         }
@@ -824,7 +886,7 @@ search_kernel(SearchArgs A) {
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>()>(A, qi, lds);
+        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0>(A, qi, lds);
         wave_sync();
         verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         wave_sync();
@@ -895,15 +957,22 @@ hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t 
 hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s) {
     const dim3 blk(a.waves_per_block * kWave);
     const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
-#define S_LAUNCH(G, NCH)                                                                          \
+#define S_LAUNCH_B(G, NCH, B)                                                                     \
     if (a.storage == UHNSW_STORE_F32)                                                             \
-        hipLaunchKernelGGL((search_kernel<G, NCH, float>), dim3(grid), blk, lds, s, a);           \
+        hipLaunchKernelGGL((search_kernel<G, NCH, float, B>), dim3(grid), blk, lds, s, a);        \
     else if (a.storage == UHNSW_STORE_BF16)                                                       \
-        hipLaunchKernelGGL((search_kernel<G, NCH, bf16_t>), dim3(grid), blk, lds, s, a);          \
+        hipLaunchKernelGGL((search_kernel<G, NCH, bf16_t, B>), dim3(grid), blk, lds, s, a);       \
     else                                                                                          \
-        hipLaunchKernelGGL((search_kernel<G, NCH, f16_t>), dim3(grid), blk, lds, s, a);
+        hipLaunchKernelGGL((search_kernel<G, NCH, f16_t, B>), dim3(grid), blk, lds, s, a);
+#define S_LAUNCH(G, NCH)        \
+    if (a.beam == 2) {          \
+        S_LAUNCH_B(G, NCH, 2)   \
+    } else {                    \
+        S_LAUNCH_B(G, NCH, 1)   \
+    }
     UHNSW_LAYOUT_SWITCH(layout, S_LAUNCH)
 #undef S_LAUNCH
+#undef S_LAUNCH_B
     return hipGetLastError();
 }
 
@@ -942,9 +1011,29 @@ int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
         }                                                                  \
     }
 UHNSW_STUBS(walk_kernel)
-UHNSW_STUBS(search_kernel)
 #undef UHNSW_STUBS
 #undef UHNSW_STUB
+
+// The fused kernel's stub by layout, storage and beam width.
+template <int B>
+const void *search_stub(int layout, int storage) {
+#define SB(G, NCH)                                                                                       \
+    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&search_kernel<G, NCH, float, B>)  \
+     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&search_kernel<G, NCH, bf16_t, B>) \
+                                   : reinterpret_cast<const void *>(&search_kernel<G, NCH, f16_t, B>))
+    switch (layout) {
+        case L8x4x1: return SB(8, 1);
+        case L8x4x2: return SB(8, 2);
+        case L8x4x4: return SB(8, 4);
+        case L16x4x4: return SB(16, 4);
+        case L32x4x4: return SB(32, 4);
+        default: return SB(64, 4);
+    }
+#undef SB
+}
+const void *search_kernel_ptr(int layout, int storage, int beam) {
+    return beam == 2 ? search_stub<2>(layout, storage) : search_stub<1>(layout, storage);
+}
 
 const void *verify_kernel_ptr(int layout) {
     switch (layout) {
