@@ -795,11 +795,11 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
                     float ms[3];
                     bool ok = true;
                     for (int rep = -1; rep < 3 && ok; ++rep) {
-                        if (pipelined) {  // 4 launches, two in flight: wall time per launch
+                        if (pipelined) {  // 6 launches, two in flight: wall time per launch
                             t.timing = 0;
                             if (rep >= 0) HIP_OR_FAIL(c, hipStreamSynchronize(s));
                             const auto t0 = std::chrono::steady_clock::now();
-                            for (int l = 0; l < 4 && ok; ++l) {
+                            for (int l = 0; l < 6 && ok; ++l) {
                                 const int j = l & 1;
                                 int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
                                                              oid[j].as<int64_t>(), od[j].as<float>(),
@@ -815,7 +815,7 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
                             HIP_OR_FAIL(c, hipStreamSynchronize(st2[1]));
                             const double dt = std::chrono::duration<double, std::milli>(
                                                   std::chrono::steady_clock::now() - t0).count();
-                            if (rep >= 0) ms[rep] = (float)(dt / 4);
+                            if (rep >= 0) ms[rep] = (float)(dt / 6);
                             continue;
                         }
                         int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
