@@ -81,6 +81,7 @@ struct uhnsw_ctx {
     struct StreamSet {
         hipStream_t stream = nullptr;
         DevBuf cand_ids, cand_keys, ncand, stats, counter;
+        DevBuf o_entry, o_ekey, o_dnb, o_dist, o_misc, o_order;  // cost-ordered launch
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
         bool timed = false;
         hipGraphExec_t gexec = nullptr;
@@ -278,6 +279,7 @@ int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
     if (!std::isfinite(prm.cutoff)) return fail(c, UHNSW_EINVAL, "cutoff must be finite");
     if (prm.t < 0 || prm.kappa < 0) return fail(c, UHNSW_EINVAL, "t and kappa must be >= 0");
     if (prm.beam_width < 1 || prm.beam_width > 2) return fail(c, UHNSW_EINVAL, "beam_width must be 1 or 2");
+    if (prm.persistent < 0 || prm.persistent > 2) return fail(c, UHNSW_EINVAL, "persistent must be 0, 1 or 2");
     for (int i = 0; i < 2; ++i)
         if (prm.beam_width * c->g[i].M0 > kUCap)
             return fail(c, UHNSW_EINVAL, "beam_width %d x 2M = %d exceeds %d lanes", prm.beam_width,
@@ -297,6 +299,7 @@ void uhnsw_default_params(uhnsw_params *p) {
     p->cutoff = 1.4f;
     p->beam_width = 1;
     p->early_abort = 1;
+    p->persistent = 2;  // cost-ordered persistent launch: same results, shorter tail
 }
 
 int uhnsw_create(int device, uhnsw_ctx **out) {
@@ -338,7 +341,8 @@ void uhnsw_destroy(uhnsw_ctx *c) {
     for (auto &S : c->sets) {
         for (auto &ev : S->ev)
             if (ev) (void)hipEventDestroy(ev);
-        DevBuf *sb[] = {&S->cand_ids, &S->cand_keys, &S->ncand, &S->stats, &S->counter};
+        DevBuf *sb[] = {&S->cand_ids, &S->cand_keys, &S->ncand, &S->stats, &S->counter, &S->o_entry,
+                        &S->o_ekey, &S->o_dnb, &S->o_dist, &S->o_misc, &S->o_order};
         for (DevBuf *b : sb) b->reset();
         if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
     }
@@ -534,6 +538,23 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         a.ncand = S->ncand.as<int32_t>();
     }
     if (prm.persistent) HIP_OR_FAIL(c, S->counter.ensure(4));
+    OrderArgs oa{};
+    if (prm.persistent == 2) {
+        const size_t q4 = (size_t)nq * 4;
+        HIP_OR_FAIL(c, S->o_entry.ensure(q4));
+        HIP_OR_FAIL(c, S->o_ekey.ensure(q4));
+        HIP_OR_FAIL(c, S->o_dnb.ensure(q4));
+        HIP_OR_FAIL(c, S->o_dist.ensure(q4));
+        HIP_OR_FAIL(c, S->o_order.ensure(q4));
+        HIP_OR_FAIL(c, S->o_misc.ensure((4 + 2 * kOrderBuckets) * 4));
+        oa.entry = S->o_entry.as<int32_t>();
+        oa.ekey = S->o_ekey.as<float>();
+        oa.dnb = S->o_dnb.as<int32_t>();
+        oa.dist = S->o_dist.as<float>();
+        oa.gsum = S->o_misc.as<float>();
+        oa.bcnt = S->o_misc.as<int32_t>() + 4;
+        oa.order = S->o_order.as<int32_t>();
+    }
 
     // the kernels of one search, in stream order
     const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
@@ -566,6 +587,14 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
             if ((e = launch_fill_i32(b.counter, 0, 1, st)) != hipSuccess) return e;
         }
         if (timed && (e = hipEventRecord(S->ev[0], st)) != hipSuccess) return e;
+        if (prm.persistent == 2) {  // descent pre-pass, then the likely-long queries first
+            if ((e = launch_fill_i32(S->o_misc.as<int32_t>(), 0, 4 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
+            if ((e = launch_order(b, oa, c->layout, st)) != hipSuccess) return e;
+            b.order = oa.order;
+            b.entry = oa.entry;
+            b.ekey = oa.ekey;
+            b.dnb = oa.dnb;
+        }
         if (prm.fused) {
             b.lds_wave_bytes = pl.search_bytes;
             if ((e = launch_search(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
@@ -778,12 +807,12 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
     hipStream_t st2[2] = {s, s == c->stream ? c->tune_stream : c->stream};
     uhnsw_params best = *prm;
     float best_ms = 1e30f;
-    const int slots_c[] = {512, 1024, 2048, 4096};
+    const int slots_c[] = {1024, 2048, 4096};
     const int wpb_c[] = {1, 2, 4};
     for (int beam = 1; beam <= (allow_beam ? 2 : 1); ++beam)
         for (int sl : slots_c)
             for (int wpb : wpb_c)
-                for (int pers = 0; pers <= 1; ++pers) {
+                for (int pers = 0; pers <= 2; ++pers) {
                     uhnsw_params t = *prm;
                     t.beam_width = beam;
                     t.visited_slots = sl;

@@ -72,12 +72,33 @@ struct SearchArgs {
     // persistent scheduling
     int32_t *counter;       // nullptr: one wave per query by grid position
     const int32_t *order;   // persistent order of queries (nullptr: 0..nq-1)
+    // descent done by a pre-pass (nullptr: the walk descends itself)
+    const int32_t *entry;   // [nq] layer-0 entry node
+    const float *ekey;      // [nq] its base-metric key
+    const int32_t *dnb;     // [nq] base distances the descent computed
+};
+
+// Cost-ordered persistent launch: a pre-pass descends every query and
+// orders the queries by their layer-0 entry distance, largest first
+// (relative to the mean of the query's graph): a far entry point predicts a
+// long walk, and starting the long walks first shortens the launch's tail.
+constexpr int kOrderBuckets = 64;
+struct OrderArgs {
+    int32_t *entry;   // [nq] out: layer-0 entry node (-1: query not searchable)
+    float *ekey;      // [nq] out: its key
+    int32_t *dnb;     // [nq] out: base distances of the descent
+    float *dist;      // [nq] out: entry distance in the graph's metric (L1, or L2)
+    float *gsum;      // [4] accumulated (sum, count) per graph; zeroed by the caller
+    int32_t *bcnt;    // [2 * kOrderBuckets] bucket counts, then cursors; zeroed by the caller
+    int32_t *order;   // [nq] out
 };
 
 // Launchers (uhnsw_kernels.hip). Return the HIP status of the launch.
 hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s);
+// descent pre-pass + ordering for the cost-ordered launch; `a` as for the walk
+hipError_t launch_order(const SearchArgs &a, const OrderArgs &o, int layout, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *dst, int32_t v, int64_t n, hipStream_t s);
 // ceiling probes (measurement only): `blocks` x 4 waves; a gather wave reads
 // iters x 32 random rows of row_bytes (128, 256 or 512) from rows of `pitch`

@@ -405,6 +405,61 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
            ef > A.ef_cap;
 }
 
+// Greedy descent over layers max_level .. 1 of graph Gr from its entry
+// point, always to the smallest (key, id) neighbour; returns the layer-0
+// entry node and its key, and adds the base distances computed to *n_b.
+// Uid / Uk: 64-entry LDS scratch of the wave.
+template <int G, int NCH, typename T, int RBV>
+__device__ int32_t descend(const DevGraph &Gr, bool l1, const T *base, int64_t pitch, const float (&qv)[NCH][4],
+                           int32_t *Uid, float *Uk, float *kout, int *n_b) {
+    const int lane = lane_id();
+    int32_t cur = Gr.entry;
+    if (lane == 0) Uid[0] = cur;
+    wave_sync();
+    base_dists<G, NCH, T, RBV>(l1, base, pitch, Uid, 1, qv, Uk);
+    wave_sync();
+    float kcur = Uk[0];
+    *n_b += 1;
+    for (int l = Gr.max_level; l >= 1; --l) {
+        for (;;) {
+            wave_sync();
+            const int64_t row = (int64_t)Gr.up_off[cur] + (l - 1);
+            const int32_t nb = lane < Gr.M ? Gr.up_adj[row * Gr.M + lane] : -1;
+            const int cnt = popc64(ballot(nb >= 0));
+            if (nb >= 0) Uid[lane] = nb;  // valid ids come first in each row
+            wave_sync();
+            base_dists<G, NCH, T, RBV>(l1, base, pitch, Uid, cnt, qv, Uk);
+            wave_sync();
+            *n_b += cnt;
+            float kb = lane < cnt ? Uk[lane] : INFINITY;
+            int32_t ib = lane < cnt ? Uid[lane] : 0x7fffffff;
+            wave_argmin(kb, ib);
+            if (cnt > 0 && key_less(kb, (uint32_t)ib, kcur, (uint32_t)cur)) {
+                cur = ib;
+                kcur = kb;
+            } else {
+                break;
+            }
+        }
+    }
+    *kout = kcur;
+    return cur;
+}
+
+// The query slice of this lane (elements c*G*4 + (lane % G)*4 + e), zero
+// beyond d.
+template <int G, int NCH>
+__device__ __forceinline__ void load_query(const float *q, int d, float (&qv)[NCH][4]) {
+    const int gl = lane_id() % G;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = c * G * 4 + gl * 4 + e;
+            qv[c][e] = j < d ? q[j] : 0.0f;
+        }
+}
+
 template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER>
 __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
@@ -444,50 +499,20 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const T *base = reinterpret_cast<const T *>(A.walk_base);
     const int64_t pitch = A.pitch;
 
-    // query slice of this lane, zero beyond d
     float qv[NCH][4];
-    {
-        const int gl = lane % G;
-        const float *q = A.queries + qi * A.d;
-#pragma unroll
-        for (int c = 0; c < NCH; ++c)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = c * G * 4 + gl * 4 + e;
-                qv[c][e] = j < A.d ? q[j] : 0.0f;
-            }
-    }
+    load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
     L.vis.clear(lane);
 
-    // ---- descent over layers max_level .. 1 (greedy, smallest (key, id))
-    int32_t cur = Gr.entry;
-    if (lane == 0) L.Uid[0] = cur;
-    wave_sync();
-    base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, 1, qv, L.Uk);
-    wave_sync();
-    float kcur = L.Uk[0];
-    int n_b = 1;
-    for (int l = Gr.max_level; l >= 1; --l) {
-        for (;;) {
-            wave_sync();
-            const int64_t row = (int64_t)Gr.up_off[cur] + (l - 1);
-            const int32_t nb = lane < Gr.M ? Gr.up_adj[row * Gr.M + lane] : -1;
-            const int cnt = popc64(ballot(nb >= 0));
-            if (nb >= 0) L.Uid[lane] = nb;  // valid ids come first in each row
-            wave_sync();
-            base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, cnt, qv, L.Uk);
-            wave_sync();
-            n_b += cnt;
-            float kb = lane < cnt ? L.Uk[lane] : INFINITY;
-            int32_t ib = lane < cnt ? L.Uid[lane] : 0x7fffffff;
-            wave_argmin(kb, ib);
-            if (cnt > 0 && key_less(kb, (uint32_t)ib, kcur, (uint32_t)cur)) {
-                cur = ib;
-                kcur = kb;
-            } else {
-                break;
-            }
-        }
+    // ---- descent over the upper layers, unless a pre-pass already did it
+    int32_t cur;
+    float kcur;
+    int n_b = 0;
+    if (A.entry) {
+        cur = A.entry[qi];
+        kcur = A.ekey[qi];
+        n_b = A.dnb[qi];
+    } else {
+        cur = descend<G, NCH, T, RBV>(Gr, l1, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
     }
     const int32_t entry0 = cur;
 
@@ -649,10 +674,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_w
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
-    int qi = fetch_query(A.counter);
-    while ((int64_t)qi < A.nq) {
+    int k = fetch_query(A.counter);
+    while ((int64_t)k < A.nq) {
+        const int64_t qi = A.order ? A.order[k] : k;
         walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, qi, lds);
-        qi = fetch_query(A.counter);
+        k = fetch_query(A.counter);
     }
 }
 
@@ -895,6 +921,86 @@ search_kernel(SearchArgs A) {
 }
 
 // ------------------------------------------------------------- utilities
+// ------------------------------------------------ cost-ordered launch
+// Pre-pass: one wave per query runs the descent the walk would run (same
+// code, same keys) and records where layer 0 starts. LDS: 64 ids + 64 keys
+// per wave.
+template <int G, int NCH, typename T>
+__global__ void __launch_bounds__(256) descend_kernel(SearchArgs A, OrderArgs O) {
+    extern __shared__ char lds_all[];
+    const int wave = threadIdx.x / kWave;
+    const int lane = lane_id();
+    int32_t *Uid = reinterpret_cast<int32_t *>(lds_all + (size_t)wave * 512);
+    float *Uk = reinterpret_cast<float *>(lds_all + (size_t)wave * 512 + 256);
+    const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
+    if (qi >= A.nq) return;
+    const float p = A.p[qi];
+    bool finite = true;
+    for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
+    if (query_bad(A, p, A.k[qi], A.ef[qi]) || ballot(!finite) != 0) {
+        if (lane == 0) {
+            O.entry[qi] = -1;
+            O.ekey[qi] = INFINITY;
+            O.dnb[qi] = 0;
+            O.dist[qi] = -1.0f;  // ordered last: the walk only flags it
+        }
+        return;
+    }
+    const int gsel = (p <= A.cutoff) ? 0 : 1;
+    const bool l1 = gsel == 0;
+    float qv[NCH][4];
+    load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
+    float kcur;
+    int n_b = 0;
+    const int32_t cur = descend<G, NCH, T, walk_rb_vgprs<T>()>(A.g[gsel], l1, reinterpret_cast<const T *>(A.walk_base),
+                                                               A.pitch, qv, Uid, Uk, &kcur, &n_b);
+    if (lane == 0) {
+        O.entry[qi] = cur;
+        O.ekey[qi] = kcur;
+        O.dnb[qi] = n_b;
+        const float dist = l1 ? kcur : sqrtf(kcur);
+        O.dist[qi] = dist;
+        atomicAdd(&O.gsum[2 * gsel], dist);
+        atomicAdd(&O.gsum[2 * gsel + 1], 1.0f);
+    }
+}
+
+// Bucket of a query: its entry distance over its graph's mean, in steps of
+// 1/32, largest first; unsearchable queries go to the last bucket.
+__device__ __forceinline__ int order_bucket(const OrderArgs &O, const SearchArgs &A, int64_t qi) {
+    const float dist = O.dist[qi];
+    if (dist < 0.0f) return kOrderBuckets - 1;
+    const int gsel = (A.p[qi] <= A.cutoff) ? 0 : 1;
+    const float mean = O.gsum[2 * gsel] / fmaxf(O.gsum[2 * gsel + 1], 1.0f);
+    const float r = mean > 0.0f ? dist / mean : 1.0f;
+    int b = (int)(r * (kOrderBuckets / 2));
+    b = b < 0 ? 0 : (b > kOrderBuckets - 2 ? kOrderBuckets - 2 : b);
+    return kOrderBuckets - 2 - b;
+}
+
+__global__ void order_count_kernel(SearchArgs A, OrderArgs O) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi < A.nq) atomicAdd(&O.bcnt[order_bucket(O, A, qi)], 1);
+}
+
+// One wave: exclusive prefix sum of the bucket counts into the cursors.
+__global__ void order_scan_kernel(OrderArgs O) {
+    const int lane = lane_id();
+    int v = lane < kOrderBuckets ? O.bcnt[lane] : 0;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane < kOrderBuckets) O.bcnt[kOrderBuckets + lane] = incl - v;
+}
+
+__global__ void order_scatter_kernel(SearchArgs A, OrderArgs O) {
+    const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi < A.nq) O.order[atomicAdd(&O.bcnt[kOrderBuckets + order_bucket(O, A, qi)], 1)] = (int32_t)qi;
+}
+
 __global__ void fill_i32_kernel(int32_t *dst, int32_t v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = v;
@@ -973,6 +1079,29 @@ hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t 
     UHNSW_LAYOUT_SWITCH(layout, S_LAUNCH)
 #undef S_LAUNCH
 #undef S_LAUNCH_B
+    return hipGetLastError();
+}
+
+hipError_t launch_order(const SearchArgs &a, const OrderArgs &o, int layout, hipStream_t s) {
+    const int wpb = 4;
+    const int grid = (int)((a.nq + wpb - 1) / wpb);
+    SearchArgs b = a;
+    b.waves_per_block = wpb;
+#define D_LAUNCH(G, NCH)                                                                                   \
+    if (a.storage == UHNSW_STORE_F32)                                                                     \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, float>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
+    else if (a.storage == UHNSW_STORE_BF16)                                                               \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, bf16_t>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
+    else                                                                                                  \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, f16_t>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o);
+    UHNSW_LAYOUT_SWITCH(layout, D_LAUNCH)
+#undef D_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)((a.nq + 255) / 256);
+    hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(256), 0, s, a, o);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kWave), 0, s, o);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, a, o);
     return hipGetLastError();
 }
 
