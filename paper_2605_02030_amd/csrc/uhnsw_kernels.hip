@@ -978,9 +978,16 @@ __device__ __forceinline__ int order_bucket(const OrderArgs &O, const SearchArgs
     return kOrderBuckets - 2 - b;
 }
 
-__global__ void order_count_kernel(SearchArgs A, OrderArgs O) {
+// Counts per bucket: a workgroup histogram in LDS, then one global add per
+// non-empty bucket and workgroup.
+__global__ void __launch_bounds__(256) order_count_kernel(SearchArgs A, OrderArgs O) {
+    __shared__ int h[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi < A.nq) atomicAdd(&O.bcnt[order_bucket(O, A, qi)], 1);
+    if (qi < A.nq) atomicAdd(&h[order_bucket(O, A, qi)], 1);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets && h[threadIdx.x] > 0) atomicAdd(&O.bcnt[threadIdx.x], h[threadIdx.x]);
 }
 
 // One wave: exclusive prefix sum of the bucket counts into the cursors.
@@ -996,9 +1003,24 @@ __global__ void order_scan_kernel(OrderArgs O) {
     if (lane < kOrderBuckets) O.bcnt[kOrderBuckets + lane] = incl - v;
 }
 
-__global__ void order_scatter_kernel(SearchArgs A, OrderArgs O) {
+// Positions: each workgroup reserves one range per non-empty bucket from the
+// global cursors and hands out places inside it through LDS counters.
+__global__ void __launch_bounds__(256) order_scatter_kernel(SearchArgs A, OrderArgs O) {
+    __shared__ int h[kOrderBuckets];
+    __shared__ int base[kOrderBuckets];
+    if (threadIdx.x < kOrderBuckets) h[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t qi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (qi < A.nq) O.order[atomicAdd(&O.bcnt[kOrderBuckets + order_bucket(O, A, qi)], 1)] = (int32_t)qi;
+    const int b = qi < A.nq ? order_bucket(O, A, qi) : 0;
+    if (qi < A.nq) atomicAdd(&h[b], 1);
+    __syncthreads();
+    if (threadIdx.x < kOrderBuckets) {
+        const int c = h[threadIdx.x];
+        base[threadIdx.x] = c > 0 ? atomicAdd(&O.bcnt[kOrderBuckets + threadIdx.x], c) : 0;
+        h[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    if (qi < A.nq) O.order[base[b] + atomicAdd(&h[b], 1)] = (int32_t)qi;
 }
 
 __global__ void fill_i32_kernel(int32_t *dst, int32_t v, int64_t n) {
