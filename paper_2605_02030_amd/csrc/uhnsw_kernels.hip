@@ -925,8 +925,12 @@ search_kernel(SearchArgs A) {
 // Pre-pass: one wave per query runs the descent the walk would run (same
 // code, same keys) and records where layer 0 starts. LDS: 64 ids + 64 keys
 // per wave.
+// Upper-layer rows hold M ids (16 here): 32 VGPRs of rows in flight cover
+// one row of FP32 neighbours at d <= 128 (the keys do not depend on how
+// many rows are in flight), and 6 waves per SIMD keep more descents going.
 template <int G, int NCH, typename T>
-__global__ void __launch_bounds__(256) descend_kernel(SearchArgs A, OrderArgs O) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) descend_kernel(SearchArgs A,
+                                                                                                  OrderArgs O) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
@@ -952,8 +956,8 @@ __global__ void __launch_bounds__(256) descend_kernel(SearchArgs A, OrderArgs O)
     load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
     float kcur;
     int n_b = 0;
-    const int32_t cur = descend<G, NCH, T, walk_rb_vgprs<T>()>(A.g[gsel], l1, reinterpret_cast<const T *>(A.walk_base),
-                                                               A.pitch, qv, Uid, Uk, &kcur, &n_b);
+    const int32_t cur = descend<G, NCH, T, 32>(A.g[gsel], l1, reinterpret_cast<const T *>(A.walk_base), A.pitch, qv,
+                                               Uid, Uk, &kcur, &n_b);
     if (lane == 0) {
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;
