@@ -91,14 +91,19 @@ typedef struct {
     int32_t early_abort;      /* exact partial-sum abort in verification      */
     int32_t visited_slots;    /* LDS visited-cache slots; 0 -> automatic      */
     int32_t waves_per_block;  /* 0 -> automatic                               */
-    int32_t persistent;       /* 0: one wave per query by grid position;
+    int32_t persistent;       /* schedule of the queries over the waves:
+                                 0: one wave per query by grid position;
                                  1: persistent launch, waves take queries
                                  from a work counter until none is left;
-                                 2 (default): the same after a pre-pass that
-                                 descends every query and orders the queries
-                                 by layer-0 entry distance, largest first
-                                 (the long walks start first, the launch's
-                                 tail shortens). Results do not change.    */
+                                 2: as 1, after a pre-pass that descends
+                                 every query and orders the queries by
+                                 layer-0 entry distance, largest first (the
+                                 long walks start first, the launch's tail
+                                 shortens);
+                                 3 (default): the pre-pass and order of 2
+                                 on the grid of 0 (grid position k takes
+                                 the k-th query of the order).
+                                 Results do not change.                     */
     int32_t timing;           /* 1: record per-kernel times (uhnsw_last_timing)*/
     int32_t fused;            /* 1: walk and verification in one kernel, C
                                  kept in LDS (the batching form)             */

@@ -279,7 +279,7 @@ int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
     if (!std::isfinite(prm.cutoff)) return fail(c, UHNSW_EINVAL, "cutoff must be finite");
     if (prm.t < 0 || prm.kappa < 0) return fail(c, UHNSW_EINVAL, "t and kappa must be >= 0");
     if (prm.beam_width < 1 || prm.beam_width > 2) return fail(c, UHNSW_EINVAL, "beam_width must be 1 or 2");
-    if (prm.persistent < 0 || prm.persistent > 2) return fail(c, UHNSW_EINVAL, "persistent must be 0, 1 or 2");
+    if (prm.persistent < 0 || prm.persistent > 3) return fail(c, UHNSW_EINVAL, "persistent must be 0 .. 3");
     for (int i = 0; i < 2; ++i)
         if (prm.beam_width * c->g[i].M0 > kUCap)
             return fail(c, UHNSW_EINVAL, "beam_width %d x 2M = %d exceeds %d lanes", prm.beam_width,
@@ -299,7 +299,7 @@ void uhnsw_default_params(uhnsw_params *p) {
     p->cutoff = 1.4f;
     p->beam_width = 1;
     p->early_abort = 1;
-    p->persistent = 2;  // cost-ordered persistent launch: same results, shorter tail
+    p->persistent = 3;  // cost-ordered launch: same results, shorter tail
 }
 
 int uhnsw_create(int device, uhnsw_ctx **out) {
@@ -537,9 +537,11 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         a.c_stride = cs;
         a.ncand = S->ncand.as<int32_t>();
     }
-    if (prm.persistent) HIP_OR_FAIL(c, S->counter.ensure(4));
+    const bool ordered = prm.persistent >= 2;
+    const bool counted = prm.persistent == 1 || prm.persistent == 2;  // 3: ordered static grid
+    if (counted) HIP_OR_FAIL(c, S->counter.ensure(4));
     OrderArgs oa{};
-    if (prm.persistent == 2) {
+    if (ordered) {
         const size_t q4 = (size_t)nq * 4;
         HIP_OR_FAIL(c, S->o_entry.ensure(q4));
         HIP_OR_FAIL(c, S->o_ekey.ensure(q4));
@@ -559,7 +561,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     // the kernels of one search, in stream order
     const int grid_all = (int)((nq + pl.wpb - 1) / pl.wpb);
     int pgrid = grid_all;
-    if (prm.persistent) {
+    if (counted) {
         int per_cu = 0;
         const void *kp =
             prm.fused ? search_kernel_ptr(c->layout, c->storage, prm.beam_width)
@@ -582,12 +584,12 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     auto enqueue = [&](hipStream_t st, bool timed) -> hipError_t {
         hipError_t e = hipSuccess;
         SearchArgs b = a;
-        if (prm.persistent) {
+        if (counted) {
             b.counter = S->counter.as<int32_t>();
             if ((e = launch_fill_i32(b.counter, 0, 1, st)) != hipSuccess) return e;
         }
         if (timed && (e = hipEventRecord(S->ev[0], st)) != hipSuccess) return e;
-        if (prm.persistent == 2) {  // descent pre-pass, then the likely-long queries first
+        if (ordered) {  // descent pre-pass, then the likely-long queries first
             if ((e = launch_fill_i32(S->o_misc.as<int32_t>(), 0, 4 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
             if ((e = launch_order(b, oa, c->layout, st)) != hipSuccess) return e;
             b.order = oa.order;
@@ -597,11 +599,11 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         }
         if (prm.fused) {
             b.lds_wave_bytes = pl.search_bytes;
-            if ((e = launch_search(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
+            if ((e = launch_search(b, c->layout, counted ? pgrid : grid_all, st)) != hipSuccess) return e;
             if (timed && (e = hipEventRecord(S->ev[1], st)) != hipSuccess) return e;
         } else {
             b.lds_wave_bytes = pl.walk_bytes;
-            if ((e = launch_walk(b, c->layout, prm.persistent ? pgrid : grid_all, st)) != hipSuccess) return e;
+            if ((e = launch_walk(b, c->layout, counted ? pgrid : grid_all, st)) != hipSuccess) return e;
             if (timed && (e = hipEventRecord(S->ev[1], st)) != hipSuccess) return e;
             b.lds_wave_bytes = pl.verify_bytes;
             b.counter = nullptr;
@@ -812,7 +814,7 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
     for (int beam = 1; beam <= (allow_beam ? 2 : 1); ++beam)
         for (int sl : slots_c)
             for (int wpb : wpb_c)
-                for (int pers = 0; pers <= 2; ++pers) {
+                for (int pers = 0; pers <= 3; ++pers) {
                     uhnsw_params t = *prm;
                     t.beam_width = beam;
                     t.visited_slots = sl;

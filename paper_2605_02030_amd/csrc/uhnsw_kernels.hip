@@ -669,8 +669,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_w
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
-        const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (qi < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, qi, lds);
+        const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
+        if (k < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, A.order ? A.order[k] : k, lds);
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
@@ -901,8 +901,9 @@ search_kernel(SearchArgs A) {
     const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits, A.vis_kbits);
     char *vlds = lds + (size_t)A.ef_cap * 8;
     if (A.counter == nullptr) {
-        const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (qi < A.nq) {
+        const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
+        const int64_t qi = k < A.nq && A.order ? A.order[k] : k;
+        if (k < A.nq) {
             const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0>(A, qi, lds);
             wave_sync();
             verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);

@@ -42,7 +42,7 @@ def test_default_params(lib):
     p = lib.default_params()
     assert abs(p.tau - 0.92) < 1e-15 and abs(p.cutoff - 1.4) < 1e-6
     assert p.beam_width == 1 and p.early_abort == 1 and p.t == 0 and p.kappa == 0
-    assert p.fused == 0 and p.persistent == 2 and p.graph == 0 and p.timing == 0
+    assert p.fused == 0 and p.persistent == 3 and p.graph == 0 and p.timing == 0
     q = lib.default_params(tau=0.5, beam_width=2)
     assert q.tau == 0.5 and q.beam_width == 2
 

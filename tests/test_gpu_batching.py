@@ -49,7 +49,8 @@ def _same(a, b):
             np.testing.assert_array_equal(x, y)
 
 
-@pytest.mark.parametrize("knobs", [dict(fused=1), dict(fused=1, persistent=1), dict(fused=1, persistent=2),
+@pytest.mark.parametrize("knobs", [dict(fused=1), dict(fused=1, persistent=0), dict(fused=1, persistent=1),
+                                   dict(fused=1, persistent=2), dict(fused=1, persistent=3, beam_width=1),
                                    dict(fused=1, persistent=2, beam_width=1, visited_slots=1024),
                                    dict(fused=1, persistent=1, waves_per_cu=2),
                                    dict(fused=1, persistent=1, beam_width=1, visited_slots=256)])

@@ -137,7 +137,8 @@ def test_cfg1_host_api_matches_device(torch_cuda, ctx1, wl1):
         np.testing.assert_array_equal(st_h[f], st_d[f])
 
 
-@pytest.mark.parametrize("knobs", [dict(persistent=1), dict(persistent=2), dict(persistent=2, waves_per_cu=3),
+@pytest.mark.parametrize("knobs", [dict(persistent=0), dict(persistent=1), dict(persistent=2),
+                                   dict(persistent=2, waves_per_cu=3), dict(persistent=3, waves_per_block=1),
                                    dict(waves_per_block=1), dict(visited_slots=64),
                                    dict(visited_slots=8192, waves_per_block=1), dict(early_abort=0)])
 def test_schedule_invariance(torch_cuda, ctx1, wl1, knobs):
