@@ -548,13 +548,13 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         HIP_OR_FAIL(c, S->o_dnb.ensure(q4));
         HIP_OR_FAIL(c, S->o_dist.ensure(q4));
         HIP_OR_FAIL(c, S->o_order.ensure(q4));
-        HIP_OR_FAIL(c, S->o_misc.ensure((4 + 2 * kOrderBuckets) * 4));
+        HIP_OR_FAIL(c, S->o_misc.ensure((6 + 2 * kOrderBuckets) * 4));
         oa.entry = S->o_entry.as<int32_t>();
         oa.ekey = S->o_ekey.as<float>();
         oa.dnb = S->o_dnb.as<int32_t>();
         oa.dist = S->o_dist.as<float>();
         oa.gsum = S->o_misc.as<float>();
-        oa.bcnt = S->o_misc.as<int32_t>() + 4;
+        oa.bcnt = S->o_misc.as<int32_t>() + 6;
         oa.order = S->o_order.as<int32_t>();
     }
 
@@ -590,7 +590,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         }
         if (timed && (e = hipEventRecord(S->ev[0], st)) != hipSuccess) return e;
         if (ordered) {  // descent pre-pass, then the likely-long queries first
-            if ((e = launch_fill_i32(S->o_misc.as<int32_t>(), 0, 4 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
+            if ((e = launch_fill_i32(S->o_misc.as<int32_t>(), 0, 6 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
             if ((e = launch_order(b, oa, c->layout, st)) != hipSuccess) return e;
             b.order = oa.order;
             b.entry = oa.entry;

@@ -78,17 +78,19 @@ struct SearchArgs {
     const int32_t *dnb;     // [nq] base distances the descent computed
 };
 
-// Cost-ordered persistent launch: a pre-pass descends every query and
-// orders the queries by their layer-0 entry distance, largest first
-// (relative to the mean of the query's graph): a far entry point predicts a
-// long walk, and starting the long walks first shortens the launch's tail.
+// Cost-ordered launch: a pre-pass descends every query and orders the
+// queries by predicted walk length, largest first: the layer-0 entry
+// distance relative to the mean of the query's graph (a far entry point
+// predicts a long walk) times ef relative to the batch's mean ef (the walk
+// expands at least ef entries). Starting the long walks first shortens the
+// launch's tail.
 constexpr int kOrderBuckets = 64;
 struct OrderArgs {
     int32_t *entry;   // [nq] out: layer-0 entry node (-1: query not searchable)
     float *ekey;      // [nq] out: its key
     int32_t *dnb;     // [nq] out: base distances of the descent
     float *dist;      // [nq] out: entry distance in the graph's metric (L1, or L2)
-    float *gsum;      // [4] accumulated (sum, count) per graph; zeroed by the caller
+    float *gsum;      // [6] out: (distance sum, count) per graph, then (ef sum, count)
     int32_t *bcnt;    // [2 * kOrderBuckets] bucket counts, then cursors; zeroed by the caller
     int32_t *order;   // [nq] out
 };

@@ -963,22 +963,51 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;
         O.dnb[qi] = n_b;
-        const float dist = l1 ? kcur : sqrtf(kcur);
-        O.dist[qi] = dist;
-        atomicAdd(&O.gsum[2 * gsel], dist);
-        atomicAdd(&O.gsum[2 * gsel + 1], 1.0f);
+        O.dist[qi] = l1 ? kcur : sqrtf(kcur);
     }
 }
 
-// Bucket of a query: its entry distance over its graph's mean, in steps of
-// 1/32, largest first; unsearchable queries go to the last bucket.
+// One workgroup: per graph the sum and count of entry distances, and the
+// sum and count of ef, over all searchable queries (fixed order, no atomics).
+__global__ void __launch_bounds__(256) order_mean_kernel(SearchArgs A, OrderArgs O) {
+    __shared__ float part[6][256 / kWave];
+    float v[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t qi = threadIdx.x; qi < A.nq; qi += blockDim.x) {
+        const float dist = O.dist[qi];
+        if (dist < 0.0f) continue;
+        const int gsel = (A.p[qi] <= A.cutoff) ? 0 : 1;
+        v[2 * gsel] += dist;
+        v[2 * gsel + 1] += 1.0f;
+        v[4] += (float)A.ef[qi];
+        v[5] += 1.0f;
+    }
+    const int wave = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        float x = v[j];
+#pragma unroll
+        for (int o = kWave / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+        if (lane == 0) part[j][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        float x = 0.0f;
+        for (int w = 0; w < (int)blockDim.x / kWave; ++w) x += part[threadIdx.x][w];
+        O.gsum[threadIdx.x] = x;
+    }
+}
+
+// Bucket of a query: predicted length r (entry distance over its graph's
+// mean times ef over the mean ef) on a log scale, 16 buckets per doubling
+// over [1/4, 4), largest first; unsearchable queries go to the last bucket.
 __device__ __forceinline__ int order_bucket(const OrderArgs &O, const SearchArgs &A, int64_t qi) {
     const float dist = O.dist[qi];
     if (dist < 0.0f) return kOrderBuckets - 1;
     const int gsel = (A.p[qi] <= A.cutoff) ? 0 : 1;
     const float mean = O.gsum[2 * gsel] / fmaxf(O.gsum[2 * gsel + 1], 1.0f);
-    const float r = mean > 0.0f ? dist / mean : 1.0f;
-    int b = (int)(r * (kOrderBuckets / 2));
+    const float mean_ef = O.gsum[4] / fmaxf(O.gsum[5], 1.0f);
+    const float r = (mean > 0.0f ? dist / mean : 1.0f) * (mean_ef > 0.0f ? (float)A.ef[qi] / mean_ef : 1.0f);
+    int b = r > 0.0f ? (int)floorf(log2f(r) * 16.0f) + 32 : 0;
     b = b < 0 ? 0 : (b > kOrderBuckets - 2 ? kOrderBuckets - 2 : b);
     return kOrderBuckets - 2 - b;
 }
@@ -1126,6 +1155,7 @@ hipError_t launch_order(const SearchArgs &a, const OrderArgs &o, int layout, hip
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)((a.nq + 255) / 256);
+    hipLaunchKernelGGL(order_mean_kernel, dim3(1), dim3(256), 0, s, a, o);
     hipLaunchKernelGGL(order_count_kernel, dim3(blocks), dim3(256), 0, s, a, o);
     hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kWave), 0, s, o);
     hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, a, o);
