@@ -37,7 +37,8 @@ extern "C" {
 
 #define UHNSW_MAX_LAYERS 32
 #define UHNSW_KMAX 256         /* largest K per query                          */
-#define UHNSW_EFMAX 1024       /* largest efSearch per query                   */
+#define UHNSW_EFMAX 2048       /* largest efSearch per query (the paper goes
+                                  to 2,000, Sec. 4.1.4)                        */
 #define UHNSW_DMAX 1024        /* largest dimension                            */
 
 /* Storage of the base vectors read by the candidate walk. Verification
@@ -153,6 +154,22 @@ const char *uhnsw_last_error(const uhnsw_ctx *ctx);
  * 2M / M, neighbour not on the layer, entry point not on the top layer,
  * d > UHNSW_DMAX, M0 > 64, a non-finite base value), ENOMEM, EDEVICE. */
 int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
+
+/* uhnsw_load_graphs from files (host paths):
+ *   vec_path: base vectors, .fbin layout: int32 n, int32 d, then n*d FP32
+ *             row-major (little-endian);
+ *   g1_path / g2_path: G1 (built under L1) / G2 (under L2), layout:
+ *             "UHG1", int32 n, int32 M, int32 max_level, int32 entry_point,
+ *             int8 level[n], then for each layer l = 0 .. max_level:
+ *             int64 n_l (n for l = 0), int64 row_ptr[n_l + 1],
+ *             int32 col[row_ptr[n_l]], and for l >= 1 int32 nodes[n_l].
+ * The files are read into host memory, checked as uhnsw_load_graphs checks
+ * its arguments, uploaded, and released.
+ * Errors: EIO (cannot open, short file, bad magic, n differs between
+ * files), EINVAL (as uhnsw_load_graphs, or sizes out of range), ENOMEM,
+ * EDEVICE. */
+int uhnsw_load_graph_files(uhnsw_ctx *ctx, const char *vec_path, const char *g1_path, const char *g2_path,
+                           int32_t storage);
 
 /* Search nq queries (host arrays, synchronous).
  *   queries [nq x d] FP32; p [nq]; k [nq]; ef [nq]; prm may be NULL.

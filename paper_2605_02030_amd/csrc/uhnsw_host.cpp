@@ -289,6 +289,100 @@ int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
 
 }  // namespace
 
+namespace {
+
+// Whole-file reader with bounds-checked takes (little-endian host).
+struct FileBuf {
+    std::vector<char> b;
+    size_t at = 0;
+    bool ok = true;
+    template <typename T>
+    T take() {
+        T v{};
+        if (at + sizeof(T) > b.size()) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, b.data() + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    template <typename T>
+    bool copy(int64_t count, std::vector<T> *out) {  // into aligned storage (the file may not be)
+        if (count < 0 || at + (size_t)count * sizeof(T) > b.size()) {
+            ok = false;
+            return false;
+        }
+        out->resize((size_t)count);
+        if (count) std::memcpy(out->data(), b.data() + at, (size_t)count * sizeof(T));
+        at += (size_t)count * sizeof(T);
+        return true;
+    }
+};
+
+bool read_file(const char *path, FileBuf *f) {
+    FILE *fp = path ? std::fopen(path, "rb") : nullptr;
+    if (!fp) return false;
+    bool good = std::fseek(fp, 0, SEEK_END) == 0;
+    const long size = good ? std::ftell(fp) : -1;
+    good = good && size >= 0 && std::fseek(fp, 0, SEEK_SET) == 0;
+    if (good) {
+        f->b.resize((size_t)size);
+        good = size == 0 || std::fread(f->b.data(), 1, (size_t)size, fp) == (size_t)size;
+    }
+    std::fclose(fp);
+    return good;
+}
+
+// Parsed graph file: owns aligned copies of every array uhnsw_graph points to.
+struct GraphFile {
+    int32_t n = 0;
+    uhnsw_graph g{};
+    std::vector<int8_t> level;
+    std::vector<std::vector<int64_t>> row_ptr;
+    std::vector<std::vector<int32_t>> col, nodes;
+};
+
+int parse_graph(uhnsw_ctx *c, const char *path, GraphFile *out) {
+    FileBuf f;
+    if (!read_file(path, &f)) return fail(c, UHNSW_EIO, "cannot read %s", path ? path : "(null)");
+    std::vector<char> magic;
+    if (!f.copy(4, &magic) || std::memcmp(magic.data(), "UHG1", 4) != 0)
+        return fail(c, UHNSW_EIO, "%s: not a UHG1 graph file", path);
+    const int32_t n = f.take<int32_t>(), M = f.take<int32_t>(), ml = f.take<int32_t>(), ep = f.take<int32_t>();
+    if (!f.ok || n < 1 || ml < 0 || ml >= UHNSW_MAX_LAYERS)
+        return fail(c, UHNSW_EIO, "%s: bad header (n=%d, max_level=%d)", path, n, ml);
+    if (!f.copy(n, &out->level)) return fail(c, UHNSW_EIO, "%s: short file (levels)", path);
+    out->n = n;
+    out->row_ptr.resize(ml + 1);
+    out->col.resize(ml + 1);
+    out->nodes.resize(ml + 1);
+    out->g.M = M;
+    out->g.max_level = ml;
+    out->g.entry_point = ep;
+    out->g.level = out->level.data();
+    for (int l = 0; l <= ml; ++l) {
+        const int64_t nl = f.take<int64_t>();
+        if (!f.ok || nl < 0 || nl > n || (l == 0 && nl != n)) return fail(c, UHNSW_EIO, "%s: bad layer %d size", path, l);
+        if (!f.copy(nl + 1, &out->row_ptr[l])) return fail(c, UHNSW_EIO, "%s: short file (layer %d rows)", path, l);
+        const int64_t ne = out->row_ptr[l][nl];
+        if (ne < 0 || ne > (int64_t)64 * n) return fail(c, UHNSW_EIO, "%s: bad edge count on layer %d", path, l);
+        if (!f.copy(ne, &out->col[l])) return fail(c, UHNSW_EIO, "%s: short file (layer %d edges)", path, l);
+        if (out->col[l].empty()) out->col[l].push_back(0);  // a valid pointer for empty layers
+        if (l >= 1) {
+            if (!f.copy(nl, &out->nodes[l])) return fail(c, UHNSW_EIO, "%s: short file (layer %d nodes)", path, l);
+            if (out->nodes[l].empty()) out->nodes[l].push_back(0);
+            out->g.nodes[l] = out->nodes[l].data();
+        }
+        out->g.n_nodes[l] = nl;
+        out->g.row_ptr[l] = out->row_ptr[l].data();
+        out->g.col[l] = out->col[l].data();
+    }
+    return UHNSW_OK;
+}
+
+}  // namespace
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -412,6 +506,32 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     c->loaded = true;
     c->failed = false;
     return UHNSW_OK;
+}
+
+int uhnsw_load_graph_files(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
+                           int32_t storage) {
+    if (!c) return UHNSW_EINVAL;
+    FileBuf vf;
+    if (!read_file(vec_path, &vf)) return fail(c, UHNSW_EIO, "cannot read %s", vec_path ? vec_path : "(null)");
+    const int32_t n = vf.take<int32_t>(), d = vf.take<int32_t>();
+    if (!vf.ok || n < 1 || d < 1 || d > UHNSW_DMAX)
+        return fail(c, UHNSW_EIO, "%s: bad header (n=%d, d=%d)", vec_path, n, d);
+    std::vector<float> base;
+    if (!vf.copy((int64_t)n * d, &base)) return fail(c, UHNSW_EIO, "%s: short file", vec_path);
+    vf.b.clear();
+    GraphFile g1, g2;
+    int r = parse_graph(c, g1_path, &g1);
+    if (r) return r;
+    if ((r = parse_graph(c, g2_path, &g2))) return r;
+    if (g1.n != n || g2.n != n) return fail(c, UHNSW_EIO, "graph files hold %d / %d nodes, vectors %d", g1.n, g2.n, n);
+    uhnsw_index idx{};
+    idx.n = n;
+    idx.d = d;
+    idx.base = base.data();
+    idx.storage = storage;
+    idx.graphs[0] = g1.g;
+    idx.graphs[1] = g2.g;
+    return uhnsw_load_graphs(c, &idx);
 }
 
 int uhnsw_get_layout(const uhnsw_ctx *c, int32_t *g, int32_t *v) {

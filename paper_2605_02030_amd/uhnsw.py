@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libuhnsw.so")
 
 UHNSW_OK, UHNSW_EINVAL, UHNSW_ENOMEM, UHNSW_EDEVICE = 0, -1, -2, -3
 UHNSW_ESTATE, UHNSW_EIO, UHNSW_EBUSY, UHNSW_EUNSUPPORTED = -4, -5, -6, -7
-UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 1024, 1024
+UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 2048, 1024
 STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
@@ -24,7 +24,7 @@ EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
-           "uhnsw_probe_gather", "uhnsw_probe_transcendental")
+           "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -102,6 +102,8 @@ uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(
 uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
                          [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
 uhnsw_probe_gather = _sig("uhnsw_probe_gather", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_double)])
+uhnsw_load_graph_files = _sig("uhnsw_load_graph_files", ctypes.c_int,
+                              [_P, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32])
 uhnsw_probe_transcendental = _sig("uhnsw_probe_transcendental", ctypes.c_int,
                                   [_P, ctypes.POINTER(ctypes.c_double)])
 
@@ -259,6 +261,12 @@ class Context:
         cus, khz = _I32(), _I32()
         self._check(uhnsw_device_info(self.h, ctypes.byref(cus), ctypes.byref(khz)))
         return cus.value, khz.value
+
+    def load_graph_files(self, vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32):
+        """Load an index from a .fbin vector file and two UHG1 graph files."""
+        self._check(uhnsw_load_graph_files(self.h, os.fsencode(vec_path), os.fsencode(g1_path),
+                                           os.fsencode(g2_path), int(storage)))
+        self.n, self.d = (int(x) for x in np.fromfile(vec_path, np.int32, 2))
 
     def probe_gather(self, row_bytes: int) -> float:
         """GB/s of random row gathers with the walk's access pattern (ceiling probe)."""

@@ -168,3 +168,30 @@ def build_graphs(wl, threads: int = 0, cache: bool = True, verbose: bool = False
     g1 = build_graph(wl.base, 1, wl.M, wl.ef_construction, wl.graph_seed, threads, cache, dg, verbose)
     g2 = build_graph(wl.base, 2, wl.M, wl.ef_construction, wl.graph_seed, threads, cache, dg, verbose)
     return g1, g2
+
+
+def save_fbin(path: str, base: np.ndarray) -> None:
+    """Base vectors as .fbin: int32 n, int32 d, then n*d FP32 row-major."""
+    base = np.ascontiguousarray(base, np.float32)
+    with open(path, "wb") as f:
+        f.write(np.array(base.shape, np.int32).tobytes())
+        f.write(base.tobytes())
+
+
+def save_graph_file(path: str, g: Graph) -> None:
+    """One graph in the UHG1 layout read by uhnsw_load_graph_files:
+    "UHG1", int32 n, M, max_level, entry_point, int8 level[n], then per layer
+    int64 n_l, int64 row_ptr[n_l + 1], int32 col[...], and for l >= 1
+    int32 nodes[n_l]."""
+    n = len(g.levels)
+    with open(path, "wb") as f:
+        f.write(b"UHG1")
+        f.write(np.array([n, g.M, g.max_level, g.entry], np.int32).tobytes())
+        f.write(np.ascontiguousarray(g.levels, np.int8).tobytes())
+        for l, L in enumerate(g.layers):
+            rp = np.ascontiguousarray(L.row_ptr, np.int64)
+            f.write(np.array([len(rp) - 1], np.int64).tobytes())
+            f.write(rp.tobytes())
+            f.write(np.ascontiguousarray(L.col, np.int32).tobytes())
+            if l >= 1:
+                f.write(np.ascontiguousarray(L.nodes, np.int32).tobytes())

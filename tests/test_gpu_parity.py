@@ -100,7 +100,7 @@ def test_cfg1_parity(torch_cuda, ctx1, wl1):
     _say("excused rows", n_exc)
 
 
-@pytest.mark.parametrize("ef", [10, 16, 33, 128, 300])
+@pytest.mark.parametrize("ef", [10, 16, 33, 128, 300, 2000])
 def test_cfg1_ef_sweep(torch_cuda, ctx1, wl1, ef):
     wl, g1, g2 = wl1
     g, v = ctx1.layout()
@@ -213,7 +213,7 @@ def test_host_api_rejects(torch_cuda, ctx1, wl1):
     q = wl.queries[:2]
     ok = dict(p=np.array([1.0, 1.0], np.float32), k=np.array([10, 10], np.int32), ef=np.array([64, 64], np.int32))
     for field, val in (("p", [0.49, 1.0]), ("p", [np.nan, 1.0]), ("p", [2.01, 1.0]), ("k", [0, 10]),
-                       ("k", [257, 10]), ("ef", [9, 64]), ("ef", [1025, 64])):
+                       ("k", [uhnsw.UHNSW_KMAX + 1, 10]), ("ef", [9, 64]), ("ef", [uhnsw.UHNSW_EFMAX + 1, 64])):
         args = dict(ok)
         args[field] = np.array(val, args[field].dtype)
         with pytest.raises(uhnsw.UhnswError) as e:

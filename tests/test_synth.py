@@ -73,3 +73,37 @@ def test_builder_thread_independent():
     for la, lb in zip(a.layers, b.layers):
         np.testing.assert_array_equal(la.row_ptr, lb.row_ptr)
         np.testing.assert_array_equal(la.col, lb.col)
+
+
+def test_index_file_layouts(tmp_path):
+    """The .fbin and UHG1 writers produce the documented layouts (read back
+    here field by field; the C loader parses the same layout on the GPU)."""
+    import synth
+    import synth.graphs as sg
+
+    wl = synth.make_workload(1, n=300, nq=4, d=8)
+    g1, _ = sg.build_graphs(wl, cache=False)
+    vp, gp = tmp_path / "v.fbin", tmp_path / "g1.uhg"
+    sg.save_fbin(str(vp), wl.base)
+    sg.save_graph_file(str(gp), g1)
+    raw = vp.read_bytes()
+    n, d = np.frombuffer(raw[:8], np.int32)
+    assert (n, d) == (300, 8)
+    np.testing.assert_array_equal(np.frombuffer(raw[8:], np.float32).reshape(n, d), wl.base)
+    b = gp.read_bytes()
+    assert b[:4] == b"UHG1"
+    n2, M, ml, ep = np.frombuffer(b[4:20], np.int32)
+    assert (n2, M, ml, ep) == (300, g1.M, g1.max_level, g1.entry)
+    at = 20
+    np.testing.assert_array_equal(np.frombuffer(b[at:at + n2], np.int8), g1.levels)
+    at += n2
+    for l, L in enumerate(g1.layers):
+        nl = int(np.frombuffer(b[at:at + 8], np.int64)[0]); at += 8
+        rp = np.frombuffer(b[at:at + 8 * (nl + 1)], np.int64); at += 8 * (nl + 1)
+        np.testing.assert_array_equal(rp, L.row_ptr)
+        col = np.frombuffer(b[at:at + 4 * rp[-1]], np.int32); at += 4 * int(rp[-1])
+        np.testing.assert_array_equal(col, L.col)
+        if l >= 1:
+            nodes = np.frombuffer(b[at:at + 4 * nl], np.int32); at += 4 * nl
+            np.testing.assert_array_equal(nodes, L.nodes)
+    assert at == len(b)
