@@ -171,6 +171,17 @@ int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
 int uhnsw_load_graph_files(uhnsw_ctx *ctx, const char *vec_path, const char *g1_path, const char *g2_path,
                            int32_t storage);
 
+/* Host-only validation: the checks uhnsw_load_graphs (resp.
+ * uhnsw_load_graph_files) makes before it touches a device, with no context
+ * and no HIP call, so an index can be vetted on a machine without a GPU.
+ * msg (may be NULL) receives the reason for a failure ("" on success),
+ * NUL-terminated and cut to msg_len bytes; the index stays the caller's.
+ * Returns UHNSW_OK, UHNSW_EINVAL (structure, as uhnsw_load_graphs) or, for
+ * the files form, UHNSW_EIO (as uhnsw_load_graph_files). */
+int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len);
+int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
+                            char *msg, int32_t msg_len);
+
 /* Search nq queries (host arrays, synchronous).
  *   queries [nq x d] FP32; p [nq]; k [nq]; ef [nq]; prm may be NULL.
  *   ids [nq x k_stride] int64 and dists [nq x k_stride] FP32 receive, per

@@ -122,13 +122,27 @@ int ctx_device(const uhnsw_ctx *c) { return c->device; }
 
 namespace {
 
-int fail(uhnsw_ctx *c, int code, const char *fmt, ...) {
+int vfail(std::string *err, int code, const char *fmt, va_list ap) {
     char buf[512];
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    *err = buf;
+    return code;
+}
+
+int fail(uhnsw_ctx *c, int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vfail(&c->err, code, fmt, ap);
     va_end(ap);
-    c->err = buf;
+    return code;
+}
+
+// The same for checks that run without a context (the message goes to *err).
+int fail(std::string *err, int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vfail(err, code, fmt, ap);
+    va_end(ap);
     return code;
 }
 
@@ -146,7 +160,7 @@ int dev_fail(uhnsw_ctx *c, hipError_t e, const char *what) {
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Validate one graph against n and the node levels; returns 0 or EINVAL.
-int check_graph(uhnsw_ctx *c, const uhnsw_graph &g, int64_t n, int which) {
+int check_graph(std::string *c, const uhnsw_graph &g, int64_t n, int which) {
     const char *nm = which == 0 ? "G1" : "G2";
     if (g.M < 1 || 2 * g.M > kWave) return fail(c, UHNSW_EINVAL, "%s: M=%d outside [1, 32]", nm, g.M);
     if (g.max_level < 0 || g.max_level >= UHNSW_MAX_LAYERS)
@@ -343,7 +357,7 @@ struct GraphFile {
     std::vector<std::vector<int32_t>> col, nodes;
 };
 
-int parse_graph(uhnsw_ctx *c, const char *path, GraphFile *out) {
+int parse_graph(std::string *c, const char *path, GraphFile *out) {
     FileBuf f;
     if (!read_file(path, &f)) return fail(c, UHNSW_EIO, "cannot read %s", path ? path : "(null)");
     std::vector<char> magic;
@@ -379,6 +393,58 @@ int parse_graph(uhnsw_ctx *c, const char *path, GraphFile *out) {
         out->g.col[l] = out->col[l].data();
     }
     return UHNSW_OK;
+}
+
+// Everything uhnsw_load_graphs checks before it touches the device.
+int check_index(std::string *err, const uhnsw_index *idx) {
+    if (!idx || !idx->base) return fail(err, UHNSW_EINVAL, "index or base is NULL");
+    if (idx->n < 1 || idx->n > INT32_MAX) return fail(err, UHNSW_EINVAL, "n=%lld outside [1, 2^31)", (long long)idx->n);
+    if (idx->d < 1 || idx->d > UHNSW_DMAX) return fail(err, UHNSW_EINVAL, "d=%d outside [1, %d]", idx->d, UHNSW_DMAX);
+    if (idx->storage < UHNSW_STORE_F32 || idx->storage > UHNSW_STORE_F16)
+        return fail(err, UHNSW_EINVAL, "unknown storage %d", idx->storage);
+    for (int i = 0; i < 2; ++i) {
+        int r = check_graph(err, idx->graphs[i], idx->n, i);
+        if (r) return r;
+    }
+    for (int64_t i = 0; i < idx->n * idx->d; ++i)
+        if (!std::isfinite(idx->base[i]))
+            return fail(err, UHNSW_EINVAL, "base value %lld is not finite", (long long)i);
+    return UHNSW_OK;
+}
+
+// The three index files, parsed into an index whose arrays this object owns.
+struct IndexFiles {
+    std::vector<float> base;
+    GraphFile g1, g2;
+    uhnsw_index idx{};
+};
+
+int read_index_files(std::string *err, const char *vec_path, const char *g1_path, const char *g2_path,
+                     int32_t storage, IndexFiles *out) {
+    FileBuf vf;
+    if (!read_file(vec_path, &vf)) return fail(err, UHNSW_EIO, "cannot read %s", vec_path ? vec_path : "(null)");
+    const int32_t n = vf.take<int32_t>(), d = vf.take<int32_t>();
+    if (!vf.ok || n < 1 || d < 1 || d > UHNSW_DMAX)
+        return fail(err, UHNSW_EIO, "%s: bad header (n=%d, d=%d)", vec_path, n, d);
+    if (!vf.copy((int64_t)n * d, &out->base)) return fail(err, UHNSW_EIO, "%s: short file", vec_path);
+    vf.b.clear();
+    int r = parse_graph(err, g1_path, &out->g1);
+    if (r) return r;
+    if ((r = parse_graph(err, g2_path, &out->g2))) return r;
+    if (out->g1.n != n || out->g2.n != n)
+        return fail(err, UHNSW_EIO, "graph files hold %d / %d nodes, vectors %d", out->g1.n, out->g2.n, n);
+    out->idx.n = n;
+    out->idx.d = d;
+    out->idx.base = out->base.data();
+    out->idx.storage = storage;
+    out->idx.graphs[0] = out->g1.g;
+    out->idx.graphs[1] = out->g2.g;
+    return UHNSW_OK;
+}
+
+int check_result(const std::string &err, int r, char *msg, int32_t msg_len) {
+    if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", r ? err.c_str() : "");
+    return r;
 }
 
 }  // namespace
@@ -462,18 +528,8 @@ const char *uhnsw_last_error(const uhnsw_ctx *c) { return c ? c->err.c_str() : g
 
 int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     if (!c) return UHNSW_EINVAL;
-    if (!idx || !idx->base) return fail(c, UHNSW_EINVAL, "index or base is NULL");
-    if (idx->n < 1 || idx->n > INT32_MAX) return fail(c, UHNSW_EINVAL, "n=%lld outside [1, 2^31)", (long long)idx->n);
-    if (idx->d < 1 || idx->d > UHNSW_DMAX) return fail(c, UHNSW_EINVAL, "d=%d outside [1, %d]", idx->d, UHNSW_DMAX);
-    if (idx->storage < UHNSW_STORE_F32 || idx->storage > UHNSW_STORE_F16)
-        return fail(c, UHNSW_EINVAL, "unknown storage %d", idx->storage);
-    for (int i = 0; i < 2; ++i) {
-        int r = check_graph(c, idx->graphs[i], idx->n, i);
-        if (r) return r;
-    }
-    for (int64_t i = 0; i < idx->n * idx->d; ++i)
-        if (!std::isfinite(idx->base[i]))
-            return fail(c, UHNSW_EINVAL, "base value %lld is not finite", (long long)i);
+    int r0 = check_index(&c->err, idx);
+    if (r0) return r0;
     HIP_OR_FAIL(c, hipSetDevice(c->device));
     c->loaded = false;
     const int layout = layout_for_dim(idx->d);
@@ -511,27 +567,23 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
 int uhnsw_load_graph_files(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
                            int32_t storage) {
     if (!c) return UHNSW_EINVAL;
-    FileBuf vf;
-    if (!read_file(vec_path, &vf)) return fail(c, UHNSW_EIO, "cannot read %s", vec_path ? vec_path : "(null)");
-    const int32_t n = vf.take<int32_t>(), d = vf.take<int32_t>();
-    if (!vf.ok || n < 1 || d < 1 || d > UHNSW_DMAX)
-        return fail(c, UHNSW_EIO, "%s: bad header (n=%d, d=%d)", vec_path, n, d);
-    std::vector<float> base;
-    if (!vf.copy((int64_t)n * d, &base)) return fail(c, UHNSW_EIO, "%s: short file", vec_path);
-    vf.b.clear();
-    GraphFile g1, g2;
-    int r = parse_graph(c, g1_path, &g1);
-    if (r) return r;
-    if ((r = parse_graph(c, g2_path, &g2))) return r;
-    if (g1.n != n || g2.n != n) return fail(c, UHNSW_EIO, "graph files hold %d / %d nodes, vectors %d", g1.n, g2.n, n);
-    uhnsw_index idx{};
-    idx.n = n;
-    idx.d = d;
-    idx.base = base.data();
-    idx.storage = storage;
-    idx.graphs[0] = g1.g;
-    idx.graphs[1] = g2.g;
-    return uhnsw_load_graphs(c, &idx);
+    IndexFiles f;
+    int r = read_index_files(&c->err, vec_path, g1_path, g2_path, storage, &f);
+    return r ? r : uhnsw_load_graphs(c, &f.idx);
+}
+
+int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len) {
+    std::string err;
+    return check_result(err, check_index(&err, idx), msg, msg_len);
+}
+
+int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
+                            char *msg, int32_t msg_len) {
+    std::string err;
+    IndexFiles f;
+    int r = read_index_files(&err, vec_path, g1_path, g2_path, storage, &f);
+    if (!r) r = check_index(&err, &f.idx);
+    return check_result(err, r, msg, msg_len);
 }
 
 int uhnsw_get_layout(const uhnsw_ctx *c, int32_t *g, int32_t *v) {

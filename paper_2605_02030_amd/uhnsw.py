@@ -24,7 +24,8 @@ EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
-           "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files")
+           "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files", "uhnsw_check_index",
+           "uhnsw_check_index_files")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -106,6 +107,9 @@ uhnsw_load_graph_files = _sig("uhnsw_load_graph_files", ctypes.c_int,
                               [_P, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32])
 uhnsw_probe_transcendental = _sig("uhnsw_probe_transcendental", ctypes.c_int,
                                   [_P, ctypes.POINTER(ctypes.c_double)])
+uhnsw_check_index = _sig("uhnsw_check_index", ctypes.c_int, [_P, ctypes.c_char_p, _I32])
+uhnsw_check_index_files = _sig("uhnsw_check_index_files", ctypes.c_int,
+                               [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, ctypes.c_char_p, _I32])
 
 
 class UhnswError(RuntimeError):
@@ -150,6 +154,34 @@ def _graph_struct(g, keep):
     return s
 
 
+def index_struct(base, g1, g2, storage: int = STORE_F32):
+    """The uhnsw_index for (base, g1, g2) and the arrays it points into (keep
+    them alive while the struct is used)."""
+    base = np.ascontiguousarray(base, np.float32)
+    keep = [base]
+    idx = uhnsw_index()
+    idx.n, idx.d = base.shape
+    idx.base = base.ctypes.data
+    idx.storage = storage
+    idx.graphs[0] = _graph_struct(g1, keep)
+    idx.graphs[1] = _graph_struct(g2, keep)
+    return idx, keep
+
+
+def check_index(idx) -> tuple[int, str]:
+    """uhnsw_check_index: (return code, reason) with no context or device."""
+    msg = ctypes.create_string_buffer(512)
+    rc = uhnsw_check_index(ctypes.byref(idx), msg, len(msg))
+    return rc, msg.value.decode()
+
+
+def check_index_files(vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32) -> tuple[int, str]:
+    """uhnsw_check_index_files: (return code, reason) with no context or device."""
+    msg = ctypes.create_string_buffer(512)
+    rc = uhnsw_check_index_files(vec_path.encode(), g1_path.encode(), g2_path.encode(), storage, msg, len(msg))
+    return rc, msg.value.decode()
+
+
 class Context:
     """One libuhnsw context on one HIP device (owns the resident index)."""
 
@@ -176,16 +208,10 @@ class Context:
     def load_graphs(self, base, g1, g2, storage: int = STORE_F32) -> None:
         """base: (n, d) FP32; g1 / g2: graphs with M, max_level, entry, levels,
         layers[l].nodes / row_ptr / col (G1 under L1, G2 under L2)."""
-        base = np.ascontiguousarray(base, np.float32)
-        keep = [base]
-        idx = uhnsw_index()
-        idx.n, idx.d = base.shape
-        idx.base = base.ctypes.data
-        idx.storage = storage
-        idx.graphs[0] = _graph_struct(g1, keep)
-        idx.graphs[1] = _graph_struct(g2, keep)
+        idx, keep = index_struct(base, g1, g2, storage)
         self._check(uhnsw_load_graphs(self.h, ctypes.byref(idx)))
-        self.n, self.d = base.shape
+        self.n, self.d = int(idx.n), int(idx.d)
+        del keep
 
     def layout(self):
         g, v = _I32(), _I32()
