@@ -19,6 +19,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "_oracle.so")
 
 F32, BF16, F16 = 0, 1, 2
+L1, L2, L05 = 1, 2, 3  # base metrics of the walk (L05: sum sqrt|x - q|)
+VARIANT_STD, VARIANT_EXT = 0, 1
 MAXL = 32
 _lib = None
 
@@ -48,7 +50,7 @@ class OrcData(ctypes.Structure):
 class OrcParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("cutoff", ctypes.c_float), ("t_param", ctypes.c_int),
                 ("kappa", ctypes.c_int), ("w", ctypes.c_int), ("early_abort", ctypes.c_int),
-                ("g", ctypes.c_int), ("v", ctypes.c_int), ("cache_slots", ctypes.c_int)]
+                ("g", ctypes.c_int), ("v", ctypes.c_int), ("cache_slots", ctypes.c_int), ("variant", ctypes.c_int)]
 
 
 class OrcStats(ctypes.Structure):
@@ -217,10 +219,11 @@ class Params:
     g: int = 8
     v: int = 4
     cache_slots: int = 0
+    variant: int = VARIANT_STD  # VARIANT_EXT: g1 = G_0.5 (L0.5), g2 = G_1 (L1), cutoff 0.6 (Sec. 4.5)
 
     def c(self) -> OrcParams:
         return OrcParams(self.tau, self.cutoff, self.t_param, self.kappa, self.w, self.early_abort,
-                         self.g, self.v, self.cache_slots)
+                         self.g, self.v, self.cache_slots, self.variant)
 
 
 def knn_search(G: Graph, D: Data, q, metric, ef, t, w=1, g=8, v=4, cache_slots=0):

@@ -133,14 +133,17 @@ static float elem(const void *x, int storage, int64_t j) {
 }
 
 /* ====================================================== base distance
- * Base metrics of the candidate walk (Sec. 3.1: G1 under L1, G2 under L2).
+ * Base metrics of the candidate walk (Sec. 3.1: G1 under L1, G2 under L2;
+ * Sec. 4.5's extended pair: G_0.5 under L0.5, G_1 under L1).
  * delta_1 = sum |x_j - q_j|, delta_2 = sum (x_j - q_j)^2 (squared L2, rank-
- * equivalent to L2). Computed in FP32 (the paper's kernels are single
- * precision, Sec. 2.1) in one fixed order, so that any implementation that
- * follows the same order gets the same bits:
+ * equivalent to L2), delta_0.5 = sum sqrt|x_j - q_j| (the L0.5 distance is
+ * its square, so the two rank alike). Computed in FP32 (the paper's kernels
+ * are single precision, Sec. 2.1) in one fixed order, so that any
+ * implementation that follows the same order gets the same bits:
  *   element j belongs to lane (j / v) mod g; each lane sums its elements in
- *   ascending j from +0 (L2 with a fused multiply-add); lanes then combine
- *   pairwise, lane l < o taking s_l + s_{l+o}, for o = g/2, g/4, ..., 1.
+ *   ascending j from +0 (L2 with a fused multiply-add; L0.5 adds the
+ *   correctly rounded FP32 square root); lanes then combine pairwise, lane
+ *   l < o taking s_l + s_{l+o}, for o = g/2, g/4, ..., 1.
  */
 float orc_base_dist(const void *x, int storage, const float *q, int d, int metric, int g, int v) {
     float s[64];
@@ -148,8 +151,10 @@ float orc_base_dist(const void *x, int storage, const float *q, int d, int metri
     for (int j = 0; j < d; j++) {
         int lane = (j / v) % g;
         float diff = elem(x, storage, j) - q[j];
-        if (metric == 1)
+        if (metric == ORC_L1)
             s[lane] = s[lane] + fabsf(diff);
+        else if (metric == ORC_L05)
+            s[lane] = s[lane] + sqrtf(fabsf(diff));
         else
             s[lane] = fmaf(diff, diff, s[lane]);
     }
@@ -424,7 +429,9 @@ int orc_verify(const orc_data *D, const float *q, float p, int K, const int32_t 
  * G2; the compare is taken in FP32), candidate generation with t candidates,
  * verification. Defaults: t = min(ef, 6K) (the paper pairs t = 300 with
  * K = 50), kappa = max(K, 2) (kappa = K by default and kappa > 1),
- * tau = 0.92.
+ * tau = 0.92. The extended variant (Sec. 4.5) runs the same steps with
+ * G_0.5 in G1's place and G_1 in G2's, and a cutoff of 0.6 (the caller's
+ * prm->cutoff).
  */
 int orc_query(const orc_graph *g1, const orc_graph *g2, const orc_data *D, const float *q, float p, int K, int ef,
               const orc_params *prm, int32_t *ids, double *S, double *dist, int32_t *c_ids, float *c_keys,
@@ -441,8 +448,9 @@ int orc_query(const orc_graph *g1, const orc_graph *g2, const orc_data *D, const
     int m = orc_m_of(prm->tau, K);
     int32_t *ci = c_ids ? c_ids : (int32_t *)malloc(sizeof(int32_t) * (size_t)t);
     float *ck = c_keys ? c_keys : (float *)malloc(sizeof(float) * (size_t)t);
-    int nc = orc_knn_search(use_g1 ? g1 : g2, D, q, use_g1 ? 1 : 2, ef, t, prm->w, prm->g, prm->v, prm->cache_slots,
-                            ci, ck, st);
+    int metric = prm->variant == ORC_VARIANT_EXT ? (use_g1 ? ORC_L05 : ORC_L1) : (use_g1 ? ORC_L1 : ORC_L2);
+    int nc = orc_knn_search(use_g1 ? g1 : g2, D, q, metric, ef, t, prm->w, prm->g, prm->v, prm->cache_slots, ci, ck,
+                            st);
     int nr = orc_verify(D, q, p, K, ci, nc, kappa, m, prm->early_abort, ids, S, dist, st);
     if (!c_ids) free(ci);
     if (!c_keys) free(ck);

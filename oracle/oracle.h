@@ -12,8 +12,9 @@
  *   orc_lp_sum / orc_lp_dist ........ pinned (closed forms p=1,2,0.5,1.5;
  *                                      norm inequalities; library cdist)
  *   orc_bruteforce .................. pinned (library cdist top-K)
- *   orc_base_dist ................... pinned (exact on integer data; FP64
- *                                      error bound; lane-order cases)
+ *   orc_base_dist ................... pinned (exact on integer data, and for
+ *                                      L0.5 on perfect-square differences;
+ *                                      FP64 error bound; lane-order cases)
  *   orc_to_bf16 / orc_to_f16 ........ pinned (numpy float16, torch bfloat16)
  *   orc_knn_search .................. pinned (ef = n on a connected graph is
  *                                      the exact base-metric top-t; lossy
@@ -31,6 +32,16 @@
 #define ORC_F32 0
 #define ORC_BF16 1
 #define ORC_F16 2
+
+/* base metrics of the walk: L1, squared L2, and L0.5 as sum sqrt|x - q| */
+#define ORC_L1 1
+#define ORC_L2 2
+#define ORC_L05 3
+
+/* index variants: the paper's default pair (G1 under L1, G2 under L2) and
+ * the extended pair of Sec. 4.5 (G_0.5 under L0.5, G_1 under L1) */
+#define ORC_VARIANT_STD 0
+#define ORC_VARIANT_EXT 1
 
 typedef struct {
     int64_t n;
@@ -60,10 +71,12 @@ typedef struct {
     int early_abort; /* partial-sum abort in verification */
     int g, v;        /* lane-group size and elements per lane-load of the base distance */
     int cache_slots; /* 0 = exact visited set; else lossy cache of this many slots (power of 2) */
+    int variant;     /* ORC_VARIANT_STD: g1 = G1 (L1), g2 = G2 (L2); ORC_VARIANT_EXT: g1 = G_0.5
+                        (L0.5), g2 = G_1 (L1) */
 } orc_params;
 
 typedef struct {
-    int32_t graph;   /* 1 or 2 */
+    int32_t graph;   /* 1 = g1, 2 = g2 */
     int32_t n_b;     /* base-metric distance evaluations (descent + layer 0) */
     int32_t n_exp;   /* layer-0 expansions */
     int32_t n_p;     /* L_p distance evaluations */

@@ -10,11 +10,13 @@ Workload shapes follow the datasets of the U-HNSW paper's evaluation
 (Sec. 4.1.1, dataset table: SIFT 128-d, GIST 960-d, GloVe 100-d, Deep-style
 96-d), with seeded stand-ins since the datasets themselves are not used.
 The query tuple (q, p) and per-query K follow the problem statement
-(Sec. 1.1 and Sec. 2.1); p ranges over [0.5, 2] (Sec. 2.1).
+(Sec. 1.1 and Sec. 2.1); p ranges over [0.5, 2] (Sec. 2.1). Workloads 6
+and 7 are the inputs of the extended variant (Sec. 4.5): the vectors,
+queries and graph seed of workloads 1 and 2, with p over [0.2, 1] instead.
 
 Seeds: workload c uses 1000*c + 1 for base vectors, +2 for queries, +3 for
 per-query p/k/ef, +4 for mixture means / per-dimension scales, +5 for the
-graph levels.
+graph levels (workloads 6 and 7 take those of 1 and 2 except +3, their own).
 """
 from __future__ import annotations
 
@@ -23,10 +25,12 @@ import hashlib
 
 import numpy as np
 
-__all__ = ["Workload", "make_workload", "p_uniform", "P_GRID", "WORKLOADS"]
+__all__ = ["Workload", "make_workload", "p_uniform", "p_uniform_ext", "P_GRID", "P_GRID_EXT", "WORKLOADS"]
 
 # p grid 0.5, 0.6, ..., 2.0 (Sec. 4.3 evaluates exactly these 16 values).
 P_GRID = np.array([(5 + j) / 10 for j in range(16)], dtype=np.float32)
+# the extended variant's range [0.2, 1] on the same 0.1 grid (Sec. 4.5)
+P_GRID_EXT = np.array([(2 + j) / 10 for j in range(9)], dtype=np.float32)
 
 WORKLOADS = {
     1: dict(n=10_000, d=32, nq=100, name="gauss-10k-d32"),
@@ -34,6 +38,8 @@ WORKLOADS = {
     3: dict(n=1_000_000, d=960, nq=1_000, name="gammafeat-1M-d960"),
     4: dict(n=1_183_514, d=100, nq=10_000, name="unitgauss-1.18M-d100"),
     5: dict(n=10_000_000, d=96, nq=2_000, name="unitgauss-10M-d96"),
+    6: dict(n=10_000, d=32, nq=100, name="gauss-10k-d32-pext", like=1),
+    7: dict(n=1_000_000, d=128, nq=10_000, name="mixture-1M-d128-pext", like=2),
 }
 
 _CHUNK = 1 << 17
@@ -80,6 +86,12 @@ def p_uniform(rng: np.random.Generator, size: int) -> np.ndarray:
     """p uniform on (0.5, 2]: p = float32(2 - 1.5 U), U in [0, 1)."""
     u = rng.random(size)
     return (2.0 - 1.5 * u).astype(np.float32)
+
+
+def p_uniform_ext(rng: np.random.Generator, size: int) -> np.ndarray:
+    """p uniform on (0.2, 1]: p = float32(1 - 0.8 U), U in [0, 1)."""
+    u = rng.random(size)
+    return (1.0 - 0.8 * u).astype(np.float32)
 
 
 def _gauss(rng, n, d):
@@ -133,16 +145,31 @@ def _size_name(n: int) -> str:
 
 def make_workload(cfg: int, n: int | None = None, nq: int | None = None,
                   d: int | None = None) -> Workload:
-    """Build workload ``cfg`` (1..5). ``n``/``nq``/``d`` override the sizes
+    """Build workload ``cfg`` (1..7). ``n``/``nq``/``d`` override the sizes
     (same distribution, same seeds) for reduced test cases."""
     spec = WORKLOADS[cfg]
     n = spec["n"] if n is None else int(n)
     nq = spec["nq"] if nq is None else int(nq)
     d = spec["d"] if d is None else int(d)
-    s0 = 1000 * cfg
-    r_base, r_q, r_par, r_aux = (_rng(s0 + i) for i in (1, 2, 3, 4))
+    like = spec.get("like", cfg)
+    s0 = 1000 * like
+    r_base, r_q, r_aux = (_rng(s0 + i) for i in (1, 2, 4))
+    r_par = _rng(1000 * cfg + 3)
 
-    if cfg == 1:
+    if cfg == 6:
+        base = _gauss(r_base, n, d)
+        queries = _gauss(r_q, nq, d)
+        p = p_uniform_ext(r_par, nq)
+        k = np.full(nq, 10, np.int32)
+        ef = np.full(nq, 128, np.int32)  # p near 0.2 needs a wider walk than workload 1's 64
+    elif cfg == 7:
+        means = r_aux.uniform(32.0, 224.0, size=(100, d))
+        base = _mixture(r_base, means, n)
+        queries = _mixture(r_q, means, nq)
+        p = P_GRID_EXT[np.arange(nq) % len(P_GRID_EXT)].copy()
+        k = np.full(nq, 10, np.int32)
+        ef = np.full(nq, 64, np.int32)
+    elif cfg == 1:
         base = _gauss(r_base, n, d)
         queries = _gauss(r_q, nq, d)
         p = p_uniform(r_par, nq)

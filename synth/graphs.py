@@ -1,4 +1,6 @@
-"""The two HNSW base graphs (G1 under L1, G2 under L2) as per-layer CSR.
+"""The two HNSW base graphs (G1 under L1, G2 under L2; or, for the extended
+variant of the U-HNSW paper's Sec. 4.5, G_0.5 under L0.5 and G_1) as
+per-layer CSR.
 
 ``build_graph`` runs the deterministic C builder in ``hnsw_build.c`` and
 returns a :class:`Graph`. Built graphs are cached on disk (keyed by the
@@ -69,7 +71,7 @@ class Layer:
 
 @dataclasses.dataclass
 class Graph:
-    metric: int               # 1 -> L1 (G1), 2 -> L2 (G2)
+    metric: int               # 1 -> L1 (G1), 2 -> L2 (G2), 3 -> L0.5 (G_0.5)
     n: int
     M: int
     ef_construction: int
@@ -156,18 +158,23 @@ def build_graph(base: np.ndarray, metric: int, M: int = 16, ef_construction: int
     g = Graph(metric=metric, n=n, M=M, ef_construction=ef_construction, seed=seed, max_level=ml,
               entry=ep, levels=levels, layers=layers)
     if verbose:
-        print(f"[synth] built G{metric} n={n} d={d} in {time.time() - t0:.1f}s", flush=True)
+        print(f"[synth] built G{ {3: '0.5'}.get(metric, metric)} n={n} d={d} in {time.time() - t0:.1f}s",
+              flush=True)
     if path is not None:
         _save(path, g)
     return g
 
 
-def build_graphs(wl, threads: int = 0, cache: bool = True, verbose: bool = False):
-    """(G1, G2) for a :class:`synth.Workload`."""
+METRIC_L1, METRIC_L2, METRIC_L05 = 1, 2, 3
+
+
+def build_graphs(wl, threads: int = 0, cache: bool = True, verbose: bool = False, extended: bool = False):
+    """(G1, G2) for a :class:`synth.Workload`; with ``extended`` the pair of
+    the extended variant, (G_0.5, G_1)."""
     dg = hashlib.sha256(np.ascontiguousarray(wl.base).tobytes()).hexdigest() if cache else None
-    g1 = build_graph(wl.base, 1, wl.M, wl.ef_construction, wl.graph_seed, threads, cache, dg, verbose)
-    g2 = build_graph(wl.base, 2, wl.M, wl.ef_construction, wl.graph_seed, threads, cache, dg, verbose)
-    return g1, g2
+    metrics = (METRIC_L05, METRIC_L1) if extended else (METRIC_L1, METRIC_L2)
+    return tuple(build_graph(wl.base, m, wl.M, wl.ef_construction, wl.graph_seed, threads, cache, dg, verbose)
+                 for m in metrics)
 
 
 def save_fbin(path: str, base: np.ndarray) -> None:

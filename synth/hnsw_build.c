@@ -1,6 +1,8 @@
 /*
  * Deterministic HNSW construction for the two U-HNSW base graphs
- * (G1 under L1, G2 under L2; U-HNSW paper, Sec. 3.1 "two HNSW indexes").
+ * (G1 under L1, G2 under L2; U-HNSW paper, Sec. 3.1), and for the extended
+ * variant's G_0.5 under L0.5 (Sec. 4.5). metric: 1 = L1, 2 = squared L2,
+ * 3 = sum sqrt|a - b| (ranks like L0.5).
  *
  * The construction itself is the HNSW algorithm the paper builds on
  * (Sec. 2.2: incremental insertion, M neighbours per node, a dynamic
@@ -85,10 +87,23 @@ static float dist_l2(const float *a, const float *b, int d) {
     return r;
 }
 
+/* sum sqrt|a - b|: the L0.5 distance's square root, ranked like it */
+static float dist_l05(const float *a, const float *b, int d) {
+    float s[16];
+    for (int u = 0; u < 16; u++) s[u] = 0.0f;
+    int j = 0;
+    for (; j + 16 <= d; j += 16)
+        for (int u = 0; u < 16; u++) s[u] += sqrtf(fabsf(a[j + u] - b[j + u]));
+    float r = 0.0f;
+    for (; j < d; j++) r += sqrtf(fabsf(a[j] - b[j]));
+    for (int u = 0; u < 16; u++) r += s[u];
+    return r;
+}
+
 static inline const float *vec(const hb_t *g, int32_t v) { return g->base + (int64_t)v * g->d; }
 
 static inline float dist(const hb_t *g, const float *a, const float *b) {
-    return g->metric == 1 ? dist_l1(a, b, g->d) : dist_l2(a, b, g->d);
+    return g->metric == 1 ? dist_l1(a, b, g->d) : g->metric == 2 ? dist_l2(a, b, g->d) : dist_l05(a, b, g->d);
 }
 
 static inline int32_t *nbrs(const hb_t *g, int32_t v, int l, int *cnt) {
@@ -334,7 +349,7 @@ static uint64_t splitmix64(uint64_t x) {
 /* ----------------------------------------------------------- public API */
 void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, uint64_t seed, int nthreads,
                int verbose) {
-    if (n < 1 || d < 1 || (metric != 1 && metric != 2) || M < 2 || M > 127 || efc < 1) return NULL;
+    if (n < 1 || d < 1 || metric < 1 || metric > 3 || M < 2 || M > 127 || efc < 1) return NULL;
     hb_t *g = (hb_t *)calloc(1, sizeof(hb_t));
     g->n = n;
     g->d = d;

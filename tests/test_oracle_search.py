@@ -24,9 +24,21 @@ def _strongly_connected(g):
     return nc == 1
 
 
+def _int_key(base, q, metric):
+    """Exact integer base keys. L0.5 (metric 3) needs every |x - q| to be a
+    perfect square (the inputs of ``sq_workload``)."""
+    dl = np.abs(base.astype(np.int64) - q.astype(np.int64)[None, :])
+    if metric == 1:
+        return dl.sum(1)
+    if metric == 2:
+        return (dl * dl).sum(1)
+    r = np.rint(np.sqrt(dl)).astype(np.int64)
+    assert (r * r == dl).all()
+    return r.sum(1)
+
+
 def _exact_base_topt(base, q, metric, t):
-    dl = base.astype(np.int64) - q.astype(np.int64)[None, :]
-    key = np.abs(dl).sum(1) if metric == 1 else (dl * dl).sum(1)
+    key = _int_key(base, q, metric)
     order = np.lexsort((np.arange(base.shape[0]), key))
     return order[:t], key[order[:t]]
 
@@ -46,6 +58,21 @@ def test_full_ef_is_exact_topt(small_int_workload, metric, w):
             assert list(ids) == list(ref_ids)
             np.testing.assert_array_equal(keys, ref_keys.astype(np.float32))
             assert st.n_exp == n  # every node expanded exactly once
+
+
+@pytest.mark.parametrize("w", [1, 2])
+def test_full_ef_is_exact_topt_l05(sq_workload, w):
+    base, queries, g, _ = sq_workload
+    assert _strongly_connected(g)
+    G, D = oracle.Graph(g), oracle.Data(base)
+    n = base.shape[0]
+    for q in queries[:8]:
+        for t in (1, 10, 57, n):
+            ids, keys, st = oracle.knn_search(G, D, q, oracle.L05, ef=n, t=t, w=w)
+            ref_ids, ref_keys = _exact_base_topt(base, q, 3, t)
+            assert list(ids) == list(ref_ids)
+            np.testing.assert_array_equal(keys, ref_keys.astype(np.float32))
+            assert st.n_exp == n
 
 
 @pytest.mark.parametrize("slots", [16, 64, 256])
@@ -103,8 +130,7 @@ def _textbook_search(g, base, q, metric, ef):
     heaps, independently of the oracle's sorted-list formulation."""
     import heapq
 
-    dl = base.astype(np.int64) - q.astype(np.int64)[None, :]
-    key = np.abs(dl).sum(1) if metric == 1 else (dl * dl).sum(1)
+    key = _int_key(base, q, metric)
     cur = g.entry
     for l in range(g.max_level, 0, -1):
         L = g.layers[l]
@@ -150,6 +176,17 @@ def test_matches_textbook_heap_search(small_int_workload, metric):
         for ef in (1, 3, 10, 32):
             ids, keys, st = oracle.knn_search(G, D, q, metric, ef=ef, t=ef)
             ref, start = _textbook_search(g, base, q, metric, ef)
+            assert list(ids) == ref[:ef]
+            assert st.entry0 == start
+
+
+def test_matches_textbook_heap_search_l05(sq_workload):
+    base, queries, g, _ = sq_workload
+    G, D = oracle.Graph(g), oracle.Data(base)
+    for q in queries:
+        for ef in (1, 3, 10, 32):
+            ids, keys, st = oracle.knn_search(G, D, q, oracle.L05, ef=ef, t=ef)
+            ref, start = _textbook_search(g, base, q, 3, ef)
             assert list(ids) == ref[:ef]
             assert st.entry0 == start
 

@@ -60,6 +60,49 @@ def test_base_dist_integer_exact(g, v):
         assert oracle.base_dist(x, q, 2, g, v) == float((dl * dl).sum())
 
 
+@pytest.mark.parametrize("g,v", [(1, 1), (8, 4), (16, 4), (64, 4), (16, 2)])
+def test_base_dist_l05_perfect_squares_exact(g, v):
+    """L0.5 base key sum sqrt|x - q|: with |x - q| a perfect square every
+    root is an exact integer and every partial sum too, so the key is the
+    integer sum in any order."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    for d in (1, 7, 32, 128, 960):
+        r = rng.integers(0, 16, size=d)
+        q = rng.integers(0, 256, size=d).astype(np.float64)
+        sign = np.where(rng.random(d) < 0.5, -1.0, 1.0)
+        x = (q + sign * r * r).astype(np.float32)
+        assert oracle.base_dist(x, q.astype(np.float32), oracle.L05, g, v) == float(r.sum())
+
+
+def test_base_dist_l05_error_bound_and_rank():
+    """Against sum sqrt|x - q| in FP64: each correctly rounded root adds at
+    most u relative, the sum gamma_k as above. Rank pin: the key's square is
+    the L0.5 distance of the FP64 definition (oracle.lp_dist at p = 0.5)."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    u = 2.0 ** -24
+    for d, g in ((32, 8), (128, 32), (960, 64), (100, 16)):
+        x = rng.standard_normal(d).astype(np.float32)
+        q = rng.standard_normal(d).astype(np.float32)
+        exact = np.sqrt(np.abs(x.astype(np.float64) - q.astype(np.float64))).sum()
+        kk = -(-d // g) + 4 + int(np.log2(g)) + 3
+        got = oracle.base_dist(x, q, oracle.L05, g, 4)
+        assert abs(got - exact) <= kk * u * exact * 1.01
+        assert abs(got * got - oracle.lp_dist(x, q, 0.5)) <= 2.1 * kk * u * exact * exact
+
+
+def test_base_dist_l05_rounded_root():
+    """The root is taken in FP32, correctly rounded, per element: |x - q| = 2
+    gives fl(sqrt 2) = 1.41421353816986083984375 (not the FP64 root 1.41421356...)."""
+    x = np.array([2.0], np.float32)
+    q = np.zeros(1, np.float32)
+    assert oracle.base_dist(x, q, oracle.L05, 1, 1) == float(np.sqrt(np.float32(2.0)))
+    assert oracle.base_dist(x, q, oracle.L05, 1, 1) == 1.41421353816986083984375
+    # two lanes (g = 2, v = 1): lane sums sqrt2 and sqrt3, then one rounded add
+    x2 = np.array([2.0, 3.0], np.float32)
+    want = float(np.float32(np.sqrt(np.float32(2.0))) + np.float32(np.sqrt(np.float32(3.0))))
+    assert oracle.base_dist(x2, np.zeros(2, np.float32), oracle.L05, 2, 1) == want
+
+
 def test_base_dist_error_bound():
     """|fl(delta) - delta| <= gamma_k * sum|terms|, k = ceil(d/g) + v + log2 g + 2."""
     rng = np.random.Generator(np.random.PCG64(11))

@@ -102,6 +102,64 @@ def test_p1_p2_stop_after_first_batch(small_int_workload):
         np.testing.assert_array_equal(r["ids"][:, :10], r["c_ids"][:, :10])
 
 
+def test_ext_stops_after_first_batch(sq_workload):
+    """Extended variant (Sec. 4.5): p = 0.5 takes G_0.5 and p = 1 takes G_1
+    (cutoff 0.6). With every |x - q| a perfect square, the L0.5 base key is
+    the exact S_0.5 and the L1 key the exact S_1, so both stop after one
+    batch with R = C[0:K], as p = 1, 2 do on the default pair."""
+    base, queries, g05, g1 = sq_workload
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(base)
+    nq = len(queries)
+    prm = oracle.Params(variant=oracle.VARIANT_EXT, cutoff=0.6)
+    for p, graph in ((0.5, 1), (1.0, 2)):
+        ps = np.full(nq, p, np.float32)
+        r = oracle.query_batch(G05, G1, D, queries, ps, np.full(nq, 10, np.int32), np.full(nq, 64, np.int32),
+                               prm, c_stride=64)
+        st = r["stats"]
+        assert (st["graph"] == graph).all()
+        assert (st["batches"] == 1).all() and (st["n_p"] == 20).all()
+        np.testing.assert_array_equal(r["ids"][:, :10], r["c_ids"][:, :10])
+        # and the result is the exact brute-force top-K (ties by id) where C reached it
+        gt, _ = oracle.bruteforce(base, queries, ps, 10)
+        assert np.mean(r["ids"][:, :10] == gt) > 0.9
+
+
+def test_ext_graph_choice_cutoff(wl6):
+    wl, g05, g1 = wl6
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(wl.base)
+    ps = np.array([0.2, 0.5, np.float32(0.6), np.nextafter(np.float32(0.6), np.float32(1)), 0.8, 1.0], np.float32)
+    n = len(ps)
+    prm = oracle.Params(variant=oracle.VARIANT_EXT, cutoff=0.6)
+    r = oracle.query_batch(G05, G1, D, wl.queries[:n], ps, np.full(n, 10, np.int32), np.full(n, 32, np.int32), prm)
+    assert list(r["stats"]["graph"]) == [1, 1, 1, 2, 2, 2]
+
+
+def test_ext_recall_and_bruteforce(wl6):
+    """p over (0.2, 1] on the extended pair: recall@10 >= 0.9; with tau > 1
+    and t = n every point is verified and the result is the brute force."""
+    wl, g05, g1 = wl6
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(wl.base)
+    prm = oracle.Params(variant=oracle.VARIANT_EXT, cutoff=0.6)
+    r = oracle.query_batch(G05, G1, D, wl.queries, wl.p, wl.k, wl.ef, prm, c_stride=128)
+    gt, _ = oracle.bruteforce(wl.base, wl.queries, wl.p, 10)
+    rec = np.mean([len(set(r["ids"][i]) & set(gt[i])) / 10 for i in range(wl.nq)])
+    rec0 = np.mean([len(set(r["c_ids"][i][:10]) & set(gt[i])) / 10 for i in range(wl.nq)])
+    assert rec >= 0.9 and rec >= rec0
+    n = 400
+    sub = oracle.Data(wl.base[:n])
+    import synth.graphs as sg
+
+    h05 = sg.build_graph(wl.base[:n], sg.METRIC_L05, M=8, ef_construction=32, seed=3, cache=False)
+    h1 = sg.build_graph(wl.base[:n], sg.METRIC_L1, M=8, ef_construction=32, seed=3, cache=False)
+    nq = 12
+    full = oracle.Params(variant=oracle.VARIANT_EXT, cutoff=0.6, tau=1.01, t_param=n)
+    r = oracle.query_batch(oracle.Graph(h05), oracle.Graph(h1), sub, wl.queries[:nq], wl.p[:nq],
+                           np.full(nq, 10, np.int32), np.full(nq, n, np.int32), full)
+    assert (r["stats"]["nc"] == n).all()
+    gt, _ = oracle.bruteforce(wl.base[:n], wl.queries[:nq], wl.p[:nq], 10)
+    np.testing.assert_array_equal(r["ids"], gt)
+
+
 def test_np_monotone_in_tau(wl1):
     wl, g1, g2 = wl1
     G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
