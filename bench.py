@@ -60,11 +60,11 @@ def recall_at_k(ids, gt_ids, qidx, K=10):
 class Form:
     """One configured search path on the resident index."""
 
-    def __init__(self, torch, uhnsw, wl, g1, g2, storage, persistent, name):
+    def __init__(self, torch, uhnsw, wl, g1, g2, storage, persistent, name, variant=0):
         self.torch, self.uhnsw, self.name = torch, uhnsw, name
         self.ctx = uhnsw.Context(0)
         t0 = time.time()
-        self.ctx.load_graphs(wl.base, g1, g2, storage=storage)
+        self.ctx.load_graphs(wl.base, g1, g2, storage=storage, variant=variant)
         log(f"{name}: index uploaded in {time.time() - t0:.1f}s")
         self.persistent = persistent
         dev = torch.device("cuda:0")
@@ -183,13 +183,13 @@ def timed(form, steps, warmup, wl, rate_khz):
 
 
 def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000, 400_000), seconds=0.5,
-            max_queries=50_000, storage=None, k=None, k_max=10, label="BF16"):
+            max_queries=50_000, storage=None, k=None, k_max=10, label="BF16", variant=0):
     """Serving form: Poisson arrivals into the continuous-batching server.
     Arrival i carries query i mod nq; each rate runs for `seconds` or
     `max_queries` arrivals, whichever is fewer. `k` gives each query's K
     (default: the workload's), `ef` one efSearch for all."""
     ctx = uhnsw.Context(0)
-    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16 if storage is None else storage)
+    ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16 if storage is None else storage, variant=variant)
     kq = wl.k if k is None else k
     out = []
     pos_of = {int(q): i for i, q in enumerate(gt["qidx"])}
@@ -222,17 +222,18 @@ def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 20
                 k=sorted(set(int(x) for x in np.unique(kq))), rates=out)
 
 
-def cpu_baseline(wl, g1, g2, ef, budget_s=15.0):
+def cpu_baseline(wl, g1, g2, ef, budget_s=15.0, variant=0):
     """The oracle (plain C, OpenMP over queries) on a bounded query sample."""
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
     G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    prm = oracle.Params(variant=variant, cutoff=0.6 if variant else 1.4)
     efa = np.full(wl.nq, ef, np.int32)
     n = 64
     while True:
         t0 = time.perf_counter()
-        oracle.query_batch(G1, G2, D, wl.queries[:n], wl.p[:n], wl.k[:n], efa[:n], threads=threads)
+        oracle.query_batch(G1, G2, D, wl.queries[:n], wl.p[:n], wl.k[:n], efa[:n], prm, threads=threads)
         dt = time.perf_counter() - t0
         if dt > budget_s / 4 or n >= wl.nq:
             break
@@ -367,6 +368,115 @@ def run_secondary(a, torch, uhnsw, sg, synth):
     print(json.dumps(out), flush=True)
 
 
+SWEEP_GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_sweep_mixture-1M-d128.npz")
+
+
+def run_sweep(a, torch, uhnsw, sg, synth):
+    """Diagnostics of the method on the headline workload (plain FP32 path,
+    whole 10,000-query launches, recall on the 200-query sample of the sweep
+    ground truth):
+      ablation: the verification ablation of Sec. 4.4 (Table 2) at p = 0.51
+          and 0.9 -- recall of the first K of C (base-metric order) vs after
+          verification, walk and verification time per launch, and the
+          verification time with early stop off (tau > 1: all t candidates);
+      t_tau: the parameter study of Sec. 4.4 (Fig. 5): t in 100..500 at the
+          default tau, tau in 0.75..0.95 at t = 300; ef = 500, K = 50, p
+          spread over the 0.1 grid;
+      cutoff: recall at each p with the walk forced onto G1 or G2 (the
+          crossover the graph-choice cutoff of Sec. 3.1 rests on).
+    One JSON line."""
+    wl = synth.make_workload(2)
+    gt = dict(np.load(SWEEP_GT_PATH))
+    if bytes(gt["digest"]).decode() != wl.digest():
+        raise SystemExit(f"{SWEEP_GT_PATH} does not match the generated workload")
+    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+    ctx = uhnsw.Context(0)
+    ctx.load_graphs(wl.base, g1, g2)
+    dev = torch.device("cuda:0")
+    nq = wl.nq
+    qidx, grid, gt_ids = gt["qidx"], gt["p"], gt["ids"]
+    grid16 = [float(v) for v in grid if abs(float(v) - 0.51) > 1e-6]
+    KM, EFM = 50, 500
+    q = torch.from_numpy(wl.queries).to(dev)
+    ids = torch.empty((nq, KM), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, KM), dtype=torch.float32, device=dev)
+    stats = torch.zeros((nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
+    cid = torch.empty((nq, EFM), dtype=torch.int32, device=dev)
+    ckey = torch.empty((nq, EFM), dtype=torch.float32, device=dev)
+
+    def gt_row(pv, s):
+        j = int(np.argmin(np.abs(grid - np.float32(pv))))
+        assert abs(float(grid[j]) - float(pv)) < 1e-6
+        return gt_ids[j, s]
+
+    def run(p_all, K, ef, steps=10, **kw):
+        tp = torch.from_numpy(np.ascontiguousarray(p_all, np.float32)).to(dev)
+        tk = torch.full((nq,), K, dtype=torch.int32, device=dev)
+        te = torch.full((nq,), ef, dtype=torch.int32, device=dev)
+        prm = uhnsw.default_params(**kw)
+        ctx.search_device(q, tp, tk, te, K, ef, ids, dists, stats, cid, ckey, params=prm)
+        torch.cuda.synchronize()
+        got, cand = ids.cpu().numpy(), cid.cpu().numpy()
+        st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(nq)
+        rec = rec_c = 0.0
+        for s, i in enumerate(qidx):
+            want = set(gt_row(p_all[i], s)[:K].tolist())
+            rec += len(want & set(got[i, :K].tolist())) / K
+            rec_c += len(want & set(cand[i, :K].tolist())) / K
+        for _ in range(2):
+            ctx.search_device(q, tp, tk, te, K, ef, ids, dists, stats, params=prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.search_device(q, tp, tk, te, K, ef, ids, dists, stats, params=prm)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        prm.timing = 1
+        ctx.search_device(q, tp, tk, te, K, ef, ids, dists, stats, params=prm)
+        w, v = ctx.last_timing()
+        return dict(recall=round(rec / len(qidx), 4), recall_first_k_of_c=round(rec_c / len(qidx), 4),
+                    qps=round(nq / dt, 1), walk_ms=round(w, 4), verify_ms=round(v, 4),
+                    mean_n_p=round(float(st["n_p"].mean()), 2), mean_n_b=round(float(st["n_b"].mean()), 1))
+
+    out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries_per_launch": nq, "recall_sample": len(qidx),
+           "ablation": [], "t_tau": {"t": [], "tau": []}, "cutoff": []}
+    for K, ef in ((50, 500), (10, 256)):
+        for pv in (0.51, 0.9):
+            p_all = np.full(nq, pv, np.float32)
+            r = run(p_all, K, ef)
+            r_ns = run(p_all, K, ef, tau=1.01)
+            row = dict(K=K, ef=ef, t=min(ef, 6 * K), p=pv, recall_after_filtering=r["recall_first_k_of_c"],
+                       recall_after_reranking=r["recall"], generation_ms=r["walk_ms"],
+                       verification_ms=r["verify_ms"], verification_no_early_stop_ms=r_ns["verify_ms"],
+                       mean_n_p=r["mean_n_p"], mean_n_p_no_early_stop=r_ns["mean_n_p"], qps=r["qps"],
+                       qps_no_early_stop=r_ns["qps"])
+            out["ablation"].append(row)
+            log("ablation", json.dumps(row))
+    p_mix = wl.p.copy()
+    for s, i in enumerate(qidx):
+        p_mix[i] = grid16[s % len(grid16)]
+    for t in (100, 200, 300, 400, 500):
+        r = run(p_mix, 50, 500, t=t)
+        out["t_tau"]["t"].append(dict(t=t, tau=0.92, recall_at_50=r["recall"], qps=r["qps"],
+                                      mean_n_p=r["mean_n_p"]))
+        log("t", json.dumps(out["t_tau"]["t"][-1]))
+    for tau in (0.75, 0.80, 0.85, 0.90, 0.92, 0.95):
+        r = run(p_mix, 50, 500, tau=tau)
+        out["t_tau"]["tau"].append(dict(t=300, tau=tau, recall_at_50=r["recall"], qps=r["qps"],
+                                        mean_n_p=r["mean_n_p"]))
+        log("tau", json.dumps(out["t_tau"]["tau"][-1]))
+    for pv in [float(v) for v in grid]:
+        p_all = np.full(nq, pv, np.float32)
+        row = {"p": round(pv, 2)}
+        for name, cutoff in (("G1", 10.0), ("G2", 0.01), ("default", 1.4)):
+            r = run(p_all, 10, 256, steps=3, cutoff=cutoff)
+            row[name] = dict(recall_at_10=r["recall"], qps=r["qps"])
+        out["cutoff"].append(row)
+        log("cutoff", json.dumps(row))
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,9 +486,13 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5),
+    ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5, 7),
                     help="2: the headline workload; 3: precision form; 4: batching form; "
-                         "5: serving form (n = 1,000,000 of its 10,000,000)")
+                         "5: serving form (n = 1,000,000 of its 10,000,000); 7: the headline vectors on "
+                         "the extended index (G_0.5 + G_1, p over 0.2..1.0)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="method diagnostics on the headline workload instead of the benchmark: the "
+                         "verification ablation, the t / tau study and per-graph recall across p")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()
@@ -394,17 +508,22 @@ def main():
     from paper_2605_02030_amd import uhnsw
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if a.workload != 2:
+    if a.sweep:
+        run_sweep(a, torch, uhnsw, sg, synth)
+        return
+    if a.workload not in (2, 7):
         run_secondary(a, torch, uhnsw, sg, synth)
         return
+    ext = a.workload == 7
+    variant = uhnsw.VARIANT_EXT if ext else uhnsw.VARIANT_STD
     t0 = time.time()
-    wl = synth.make_workload(2)
+    wl = synth.make_workload(a.workload)
     log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq} ({time.time() - t0:.1f}s)")
-    gt = dict(np.load(GT_PATH))
+    gt = dict(np.load(GT_PATH)) if not ext else gt_for(wl)
     if bytes(gt["digest"]).decode() != wl.digest():
         raise SystemExit("ground-truth file does not match the generated workload")
     t0 = time.time()
-    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True, extended=ext)
     log(f"graphs ready in {time.time() - t0:.1f}s")
 
     if a.copy_probe:
@@ -422,7 +541,7 @@ def main():
     probes = None
     for name in [f.strip() for f in a.forms.split(",") if f.strip()]:
         storage, persistent, elem = specs[name]
-        f = Form(torch, uhnsw, wl, g1, g2, storage, persistent, name)
+        f = Form(torch, uhnsw, wl, g1, g2, storage, persistent, name, variant)
         f.row_bytes_per_elem = elem
         num_cus, rate_khz = f.ctx.device_info()
         if name == "fp32":  # ceiling probes on the resident FP32 rows (512 B per row)
@@ -475,25 +594,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "mixture-1M-d128", "n": wl.n, "d": wl.d, "queries_per_step": wl.nq,
-                   "k": 10, "p": "grid 0.5..2.0 cycling", "M": 16, "efConstruction": 200,
-                   "efSearch": m["ef"], "form": main_name},
+        "config": {"workload": wl.name, "n": wl.n, "d": wl.d, "queries_per_step": wl.nq,
+                   "k": 10, "p": "grid 0.2..1.0 cycling" if ext else "grid 0.5..2.0 cycling", "M": 16,
+                   "efConstruction": 200, "efSearch": m["ef"], "form": main_name,
+                   "index": "extended: G_0.5 (L0.5) + G_1, cutoff 0.6" if ext else "G1 (L1) + G2 (L2), cutoff 1.4"},
         "recall_at_10": m["recall_at_10"],
         "p50_ms": m["p50_ms"],
         "p99_ms": m["p99_ms"],
         "roofline": {"bound": "hbm", "achieved": round(ach_main, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach_main / HBM_PEAK_GBS, 4),
                      "traffic": (TRAFFIC["bytes_per_launch"] if kernel_hash == TRAFFIC["kernel_sha256_prefix"]
-                                 and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" else None),
+                                 and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" and not ext else None),
                      "kernel": "walk_kernel", "walk_ms": m["walk_ms"]},
         "probes": probes,
         "forms": forms,
     }
     if not a.no_serving:
-        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, forms[main_name]["ef"])
+        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, forms[main_name]["ef"], variant=variant)
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, g1, g2, m["ef"])
+        out["cpu_baseline"] = cpu_baseline(wl, g1, g2, m["ef"], variant=variant)
     print(json.dumps(out), flush=True)
 
 

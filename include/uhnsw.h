@@ -7,7 +7,9 @@
  * p in [0.5, 2]. Method (Sec. 3.1, Algorithm 1): pick G1 (an HNSW graph
  * built under L1) when p <= 1.4, else G2 (under L2); run HNSW's KnnSearch on
  * it to get t candidates C ordered by the base metric; verify C in batches
- * of kappa under L_p and stop once |R_new n R| / K >= tau.
+ * of kappa under L_p and stop once |R_new n R| / K >= tau. The extended
+ * variant (Sec. 4.5) serves p in [0.2, 1] with G_0.5 (built under L0.5) in
+ * G1's place, G_1 (under L1) in G2's, and a cutoff of 0.6.
  *
  * Conventions for every entry point:
  *   - plain C; no exception crosses the boundary;
@@ -72,20 +74,31 @@ typedef struct {
     const int32_t *col[UHNSW_MAX_LAYERS];
 } uhnsw_graph;
 
+/* Index variants (graph pair, base metrics, p range, default cutoff). */
+#define UHNSW_VARIANT_STD 0    /* G1 under L1, G2 under L2; p in [0.5, 2];
+                                  cutoff 1.4 (Sec. 3.1)                        */
+#define UHNSW_VARIANT_EXT 1    /* G_0.5 under L0.5 (walk key sum sqrt|x - q|),
+                                  G_1 under L1; p in [0.2, 1]; cutoff 0.6
+                                  (Sec. 4.5)                                   */
+
 /* The resident index: base vectors (host, n x d FP32 row-major) and the two
- * base graphs, graphs[0] = G1 (built under L1), graphs[1] = G2 (under L2). */
+ * base graphs, graphs[0] = G1 (built under L1), graphs[1] = G2 (under L2);
+ * for UHNSW_VARIANT_EXT graphs[0] = G_0.5 and graphs[1] = G_1. */
 typedef struct {
     int64_t n;
     int32_t d;
     const float *base;
     int32_t storage;          /* UHNSW_STORE_* for the walk                   */
     uhnsw_graph graphs[2];
+    int32_t variant;          /* UHNSW_VARIANT_*; 0 (zero-initialised) = STD  */
 } uhnsw_index;
 
 /* Algorithm 1's parameters (Sec. 3.1) and execution knobs. */
 typedef struct {
     double tau;               /* early-termination threshold, default 0.92    */
-    float cutoff;             /* G1 when p <= cutoff (FP32 compare), 1.4      */
+    float cutoff;             /* graphs[0] when p <= cutoff (FP32 compare);
+                                 0 -> the index's default (1.4, or 0.6 for
+                                 the extended variant); negative: EINVAL     */
     int32_t t;                /* candidates; 0 -> min(ef, 6K), else min(ef,t) */
     int32_t kappa;            /* batch size; 0 -> max(K, 2)                   */
     int32_t beam_width;       /* nodes expanded per walk step, 1 = HNSW       */
@@ -117,7 +130,7 @@ typedef struct {
 
 /* Per-query counters (the N_b / N_p of the paper's cost model, Eq. 1). */
 typedef struct {
-    int32_t graph;            /* 1 = G1, 2 = G2                               */
+    int32_t graph;            /* 1 = graphs[0] (G1), 2 = graphs[1] (G2)       */
     int32_t n_b;              /* base-metric distances (descent + layer 0)    */
     int32_t n_exp;            /* layer-0 expansions                           */
     int32_t n_p;              /* L_p distances evaluated                      */
@@ -152,13 +165,15 @@ const char *uhnsw_last_error(const uhnsw_ctx *ctx);
  * row pitch (zeros) and, for BF16/F16 storage, a converted walk copy.
  * Errors: EINVAL (any structural violation: id out of range, degree above
  * 2M / M, neighbour not on the layer, entry point not on the top layer,
- * d > UHNSW_DMAX, M0 > 64, a non-finite base value), ENOMEM, EDEVICE. */
+ * d > UHNSW_DMAX, M0 > 64, a non-finite base value, an unknown variant),
+ * ENOMEM, EDEVICE. */
 int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
 
 /* uhnsw_load_graphs from files (host paths):
  *   vec_path: base vectors, .fbin layout: int32 n, int32 d, then n*d FP32
  *             row-major (little-endian);
- *   g1_path / g2_path: G1 (built under L1) / G2 (under L2), layout:
+ *   g1_path / g2_path: graphs[0] / graphs[1] of `variant` (G1 / G2, or
+ *             G_0.5 / G_1), layout:
  *             "UHG1", int32 n, int32 M, int32 max_level, int32 entry_point,
  *             int8 level[n], then for each layer l = 0 .. max_level:
  *             int64 n_l (n for l = 0), int64 row_ptr[n_l + 1],
@@ -169,7 +184,7 @@ int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
  * files), EINVAL (as uhnsw_load_graphs, or sizes out of range), ENOMEM,
  * EDEVICE. */
 int uhnsw_load_graph_files(uhnsw_ctx *ctx, const char *vec_path, const char *g1_path, const char *g2_path,
-                           int32_t storage);
+                           int32_t storage, int32_t variant);
 
 /* Host-only validation: the checks uhnsw_load_graphs (resp.
  * uhnsw_load_graph_files) makes before it touches a device, with no context
@@ -180,14 +195,15 @@ int uhnsw_load_graph_files(uhnsw_ctx *ctx, const char *vec_path, const char *g1_
  * the files form, UHNSW_EIO (as uhnsw_load_graph_files). */
 int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len);
 int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
-                            char *msg, int32_t msg_len);
+                            int32_t variant, char *msg, int32_t msg_len);
 
 /* Search nq queries (host arrays, synchronous).
  *   queries [nq x d] FP32; p [nq]; k [nq]; ef [nq]; prm may be NULL.
  *   ids [nq x k_stride] int64 and dists [nq x k_stride] FP32 receive, per
  *   row, min(k[i], |C_i|) results ascending by (L_p distance, id); the rest
  *   of the row is id -1, dist +inf. stats [nq] may be NULL.
- * Errors: EINVAL (NULL pointer, nq < 0, p not finite or outside [0.5, 2],
+ * Errors: EINVAL (NULL pointer, nq < 0, p not finite or outside the
+ * index's range ([0.5, 2]; [0.2, 1] for UHNSW_VARIANT_EXT),
  * k < 1 or > UHNSW_KMAX, ef < k or > UHNSW_EFMAX, k_stride < max k, a
  * non-finite query value),
  * ESTATE (no index), ENOMEM, EDEVICE. */
@@ -306,7 +322,8 @@ void uhnsw_serve_default_config(uhnsw_serve_config *cfg);
 int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out);
 
 /* Admit one query (copied; q has d floats). Thread-safe.
- * Errors: EINVAL (p, k, ef out of range or q not finite), EBUSY (no free
+ * Errors: EINVAL (p outside the index's range, k, ef out of range or q not
+ * finite), EBUSY (no free
  * slot: retry after polling), ESTATE (stopping), or a sticky device error. */
 int uhnsw_serve_submit(uhnsw_server *srv, const float *q, float p, int32_t k, int32_t ef, uint64_t tag);
 

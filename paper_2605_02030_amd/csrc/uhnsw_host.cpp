@@ -69,6 +69,7 @@ struct uhnsw_ctx {
     // index
     int64_t n = 0;
     int32_t d = 0, storage = 0, layout = 0;
+    int32_t variant = UHNSW_VARIANT_STD;
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
     GraphDev g[2];
@@ -116,6 +117,10 @@ struct uhnsw_ctx {
 };
 
 namespace uhnsw {
+bool p_in_range(int variant, float p) {
+    return variant == UHNSW_VARIANT_EXT ? (p >= 0.2f && p <= 1.0f) : (p >= 0.5f && p <= 2.0f);
+}
+int ctx_variant(const uhnsw_ctx *c) { return c->variant; }
 int ctx_dim(const uhnsw_ctx *c) { return c->d; }
 int ctx_device(const uhnsw_ctx *c) { return c->device; }
 }  // namespace uhnsw
@@ -290,7 +295,8 @@ int ensure_mtab(uhnsw_ctx *c, double tau) {
 
 int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
     if (!(prm.tau > 0.0) || !std::isfinite(prm.tau)) return fail(c, UHNSW_EINVAL, "tau must be positive");
-    if (!std::isfinite(prm.cutoff)) return fail(c, UHNSW_EINVAL, "cutoff must be finite");
+    if (!std::isfinite(prm.cutoff) || prm.cutoff < 0.0f)
+        return fail(c, UHNSW_EINVAL, "cutoff must be finite and >= 0 (0: the index's default)");
     if (prm.t < 0 || prm.kappa < 0) return fail(c, UHNSW_EINVAL, "t and kappa must be >= 0");
     if (prm.beam_width < 1 || prm.beam_width > 2) return fail(c, UHNSW_EINVAL, "beam_width must be 1 or 2");
     if (prm.persistent < 0 || prm.persistent > 3) return fail(c, UHNSW_EINVAL, "persistent must be 0 .. 3");
@@ -402,6 +408,8 @@ int check_index(std::string *err, const uhnsw_index *idx) {
     if (idx->d < 1 || idx->d > UHNSW_DMAX) return fail(err, UHNSW_EINVAL, "d=%d outside [1, %d]", idx->d, UHNSW_DMAX);
     if (idx->storage < UHNSW_STORE_F32 || idx->storage > UHNSW_STORE_F16)
         return fail(err, UHNSW_EINVAL, "unknown storage %d", idx->storage);
+    if (idx->variant != UHNSW_VARIANT_STD && idx->variant != UHNSW_VARIANT_EXT)
+        return fail(err, UHNSW_EINVAL, "unknown variant %d", idx->variant);
     for (int i = 0; i < 2; ++i) {
         int r = check_graph(err, idx->graphs[i], idx->n, i);
         if (r) return r;
@@ -420,7 +428,7 @@ struct IndexFiles {
 };
 
 int read_index_files(std::string *err, const char *vec_path, const char *g1_path, const char *g2_path,
-                     int32_t storage, IndexFiles *out) {
+                     int32_t storage, int32_t variant, IndexFiles *out) {
     FileBuf vf;
     if (!read_file(vec_path, &vf)) return fail(err, UHNSW_EIO, "cannot read %s", vec_path ? vec_path : "(null)");
     const int32_t n = vf.take<int32_t>(), d = vf.take<int32_t>();
@@ -437,6 +445,7 @@ int read_index_files(std::string *err, const char *vec_path, const char *g1_path
     out->idx.d = d;
     out->idx.base = out->base.data();
     out->idx.storage = storage;
+    out->idx.variant = variant;
     out->idx.graphs[0] = out->g1.g;
     out->idx.graphs[1] = out->g2.g;
     return UHNSW_OK;
@@ -456,7 +465,7 @@ void uhnsw_default_params(uhnsw_params *p) {
     if (!p) return;
     std::memset(p, 0, sizeof *p);
     p->tau = 0.92;
-    p->cutoff = 1.4f;
+    p->cutoff = 0.0f;  // the index's default: 1.4, or 0.6 for the extended pair
     p->beam_width = 1;
     p->early_abort = 1;
     p->persistent = 3;  // cost-ordered launch: same results, shorter tail
@@ -531,6 +540,22 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     int r0 = check_index(&c->err, idx);
     if (r0) return r0;
     HIP_OR_FAIL(c, hipSetDevice(c->device));
+    // Searches still in flight read the buffers about to be replaced, and
+    // captured launch graphs hold the old index's pointers, sizes and kernel
+    // variant as baked arguments: wait for the device, then drop the graphs
+    // so the next graph search captures afresh.
+    HIP_OR_FAIL(c, hipDeviceSynchronize());
+    for (auto &S : c->sets)
+        if (S->gexec) {
+            (void)hipGraphExecDestroy(S->gexec);
+            S->gexec = nullptr;
+            S->gkey = GraphKey{};
+        }
+    if (c->hgexec) {
+        (void)hipGraphExecDestroy(c->hgexec);
+        c->hgexec = nullptr;
+        c->hgkey = GraphKey{};
+    }
     c->loaded = false;
     const int layout = layout_for_dim(idx->d);
     const LayoutInfo li = layout_info(layout);
@@ -557,6 +582,7 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     c->n = n;
     c->d = idx->d;
     c->storage = idx->storage;
+    c->variant = idx->variant;
     c->layout = layout;
     c->pitch = pitch;
     c->loaded = true;
@@ -565,10 +591,10 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
 }
 
 int uhnsw_load_graph_files(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
-                           int32_t storage) {
+                           int32_t storage, int32_t variant) {
     if (!c) return UHNSW_EINVAL;
     IndexFiles f;
-    int r = read_index_files(&c->err, vec_path, g1_path, g2_path, storage, &f);
+    int r = read_index_files(&c->err, vec_path, g1_path, g2_path, storage, variant, &f);
     return r ? r : uhnsw_load_graphs(c, &f.idx);
 }
 
@@ -578,10 +604,10 @@ int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len) {
 }
 
 int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
-                            char *msg, int32_t msg_len) {
+                            int32_t variant, char *msg, int32_t msg_len) {
     std::string err;
     IndexFiles f;
-    int r = read_index_files(&err, vec_path, g1_path, g2_path, storage, &f);
+    int r = read_index_files(&err, vec_path, g1_path, g2_path, storage, variant, &f);
     if (!r) r = check_index(&err, &f.idx);
     return check_result(err, r, msg, msg_len);
 }
@@ -670,7 +696,9 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     a.nq = nq;
     a.k_max = k_max;
     a.ef_max = ef_max;
-    a.cutoff = prm.cutoff;
+    // Sec. 3.1's 1.4, or Sec. 4.5's 0.6 for the extended pair
+    a.cutoff = prm.cutoff > 0.0f ? prm.cutoff : (c->variant == UHNSW_VARIANT_EXT ? 0.6f : 1.4f);
+    a.ext = c->variant == UHNSW_VARIANT_EXT;
     a.t_param = prm.t;
     a.kappa_param = prm.kappa;
     a.beam = prm.beam_width;
@@ -736,8 +764,8 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     if (counted) {
         int per_cu = 0;
         const void *kp =
-            prm.fused ? search_kernel_ptr(c->layout, c->storage, prm.beam_width)
-                      : walk_kernel_ptr(c->layout, c->storage);
+            prm.fused ? search_kernel_ptr(c->layout, c->storage, prm.beam_width, a.ext != 0)
+                      : walk_kernel_ptr(c->layout, c->storage, a.ext != 0);
         const size_t lds_block = (size_t)(prm.fused ? pl.search_bytes : pl.walk_bytes) * pl.wpb;
         bool found = false;
         for (auto &o : c->occ)
@@ -1059,8 +1087,9 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     if (!queries || !p || !k || !ef || !ids || !dists) return fail(c, UHNSW_EINVAL, "NULL array argument");
     int k_max = 0, ef_max = 0;
     for (int64_t i = 0; i < nq; ++i) {
-        if (!std::isfinite(p[i]) || p[i] < 0.5f || p[i] > 2.0f)
-            return fail(c, UHNSW_EINVAL, "p[%lld]=%g outside [0.5, 2]", (long long)i, (double)p[i]);
+        if (!std::isfinite(p[i]) || !p_in_range(c->variant, p[i]))
+            return fail(c, UHNSW_EINVAL, "p[%lld]=%g outside %s", (long long)i, (double)p[i],
+                        c->variant == UHNSW_VARIANT_EXT ? "[0.2, 1]" : "[0.5, 2]");
         if (k[i] < 1 || k[i] > UHNSW_KMAX)
             return fail(c, UHNSW_EINVAL, "k[%lld]=%d outside [1, %d]", (long long)i, k[i], UHNSW_KMAX);
         if (ef[i] < k[i] || ef[i] > UHNSW_EFMAX)

@@ -76,6 +76,9 @@ struct SearchArgs {
     const int32_t *entry;   // [nq] layer-0 entry node
     const float *ekey;      // [nq] its base-metric key
     const int32_t *dnb;     // [nq] base distances the descent computed
+    // index variant: 0 = G1 (L1) / G2 (L2), 1 = G_0.5 (L0.5) / G_1 (L1);
+    // picks the kernel instantiation, read on the host only
+    int32_t ext;
 };
 
 // Cost-ordered launch: a pre-pass descends every query and orders the
@@ -111,10 +114,12 @@ hipError_t launch_trans_probe(int blocks, int iters, float *sink, hipStream_t s)
 hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
 int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits);
 int verify_lds_bytes(int kv_cap);
-const void *walk_kernel_ptr(int layout, int storage);
+const void *walk_kernel_ptr(int layout, int storage, bool ext);
 const void *verify_kernel_ptr(int layout);
-const void *search_kernel_ptr(int layout, int storage, int beam);
+const void *search_kernel_ptr(int layout, int storage, int beam, bool ext);
 int ctx_dim(const uhnsw_ctx *c);
+int ctx_variant(const uhnsw_ctx *c);
+bool p_in_range(int variant, float p);  // the index variant's p range
 int ctx_device(const uhnsw_ctx *c);
 
 }  // namespace uhnsw

@@ -116,10 +116,16 @@ struct Elem<f16_t> {
 };
 
 // ----------------------------------------------------------- base metric
+// Base metrics of the walk: L1, squared L2, and L0.5 as sum sqrt|x - q| (the
+// L0.5 distance is its square; the extended index of Sec. 4.5 walks G_0.5
+// under it). Each lane sums its elements in ascending order, then the lane
+// group combines pairwise.
+constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3;
+
 // keys[r] = delta(row ids[r], q) for r < nrows. All lanes must call. The
 // loads of up to RB row-steps are issued before any arithmetic so that a
 // whole neighbour list is in flight at once.
-template <int G, int NCH, typename T, bool L1, int RBV>
+template <int G, int NCH, typename T, int MET, int RBV>
 __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64_t pitch,
                                                const int32_t *ids, int nrows, const float (&qv)[NCH][4],
                                                float *keys) {
@@ -153,10 +159,12 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
                     const float dlt = x[e] - qv[c][e];
-                    if (L1)
+                    if (MET == kMetL1)
                         s = s + fabsf(dlt);
-                    else
+                    else if (MET == kMetL2)
                         s = __builtin_fmaf(dlt, dlt, s);
+                    else
+                        s = s + sqrtf(fabsf(dlt));  // correctly rounded root
                 }
             }
             s = group_sum<G>(s);
@@ -166,13 +174,15 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
     }
 }
 
-template <int G, int NCH, typename T, int RBV>
-__device__ __forceinline__ void base_dists(bool l1, const T *base, int64_t pitch, const int32_t *ids, int nrows,
+// lo: the query walks graph 0 (G1, or G_0.5 when EXT) rather than graph 1
+// (G2, or G_1 when EXT).
+template <int G, int NCH, typename T, int RBV, bool EXT>
+__device__ __forceinline__ void base_dists(bool lo, const T *base, int64_t pitch, const int32_t *ids, int nrows,
                                            const float (&qv)[NCH][4], float *keys) {
-    if (l1)
-        rows_base_dist<G, NCH, T, true, RBV>(base, pitch, ids, nrows, qv, keys);
+    if (lo)
+        rows_base_dist<G, NCH, T, EXT ? kMetL05 : kMetL1, RBV>(base, pitch, ids, nrows, qv, keys);
     else
-        rows_base_dist<G, NCH, T, false, RBV>(base, pitch, ids, nrows, qv, keys);
+        rows_base_dist<G, NCH, T, EXT ? kMetL1 : kMetL2, RBV>(base, pitch, ids, nrows, qv, keys);
 }
 
 // --------------------------------------------------- sorted-list insert
@@ -400,23 +410,26 @@ __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kb
     return L;
 }
 
+// p outside the index's range ([0.5, 2]; [0.2, 1] for the extended pair)
+// or NaN, K or ef outside their bounds.
+template <bool EXT>
 __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, int ef) {
-    return !(p >= 0.5f && p <= 2.0f) || K < 1 || K > A.k_max || K > UHNSW_KMAX || ef < K || ef > A.ef_max ||
-           ef > A.ef_cap;
+    const bool p_ok = EXT ? (p >= 0.2f && p <= 1.0f) : (p >= 0.5f && p <= 2.0f);
+    return !p_ok || K < 1 || K > A.k_max || K > UHNSW_KMAX || ef < K || ef > A.ef_max || ef > A.ef_cap;
 }
 
 // Greedy descent over layers max_level .. 1 of graph Gr from its entry
 // point, always to the smallest (key, id) neighbour; returns the layer-0
 // entry node and its key, and adds the base distances computed to *n_b.
 // Uid / Uk: 64-entry LDS scratch of the wave.
-template <int G, int NCH, typename T, int RBV>
-__device__ int32_t descend(const DevGraph &Gr, bool l1, const T *base, int64_t pitch, const float (&qv)[NCH][4],
+template <int G, int NCH, typename T, int RBV, bool EXT>
+__device__ int32_t descend(const DevGraph &Gr, bool lo, const T *base, int64_t pitch, const float (&qv)[NCH][4],
                            int32_t *Uid, float *Uk, float *kout, int *n_b) {
     const int lane = lane_id();
     int32_t cur = Gr.entry;
     if (lane == 0) Uid[0] = cur;
     wave_sync();
-    base_dists<G, NCH, T, RBV>(l1, base, pitch, Uid, 1, qv, Uk);
+    base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, Uid, 1, qv, Uk);
     wave_sync();
     float kcur = Uk[0];
     *n_b += 1;
@@ -428,7 +441,7 @@ __device__ int32_t descend(const DevGraph &Gr, bool l1, const T *base, int64_t p
             const int cnt = popc64(ballot(nb >= 0));
             if (nb >= 0) Uid[lane] = nb;  // valid ids come first in each row
             wave_sync();
-            base_dists<G, NCH, T, RBV>(l1, base, pitch, Uid, cnt, qv, Uk);
+            base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, Uid, cnt, qv, Uk);
             wave_sync();
             *n_b += cnt;
             float kb = lane < cnt ? Uk[lane] : INFINITY;
@@ -460,7 +473,7 @@ __device__ __forceinline__ void load_query(const float *q, int d, float (&qv)[NC
         }
 }
 
-template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER>
+template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER, bool EXT>
 __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
@@ -473,7 +486,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     float *ckey = A.cand_keys ? A.cand_keys + qi * A.c_stride : nullptr;
     bool finite = true;
     for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
-    const bool bad = query_bad(A, p, K, ef) || ballot(!finite) != 0;
+    const bool bad = query_bad<EXT>(A, p, K, ef) || ballot(!finite) != 0;
     if (bad) {
         if (cid)
             for (int i = lane; i < A.c_stride; i += kWave) {
@@ -492,7 +505,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     }
     const int gsel = (p <= A.cutoff) ? 0 : 1;
     const DevGraph &Gr = A.g[gsel];
-    const bool l1 = gsel == 0;
+    const bool lo = gsel == 0;
     const int tp = A.t_param > 0 ? A.t_param : 6 * K;
     int t = ef < tp ? ef : tp;
     if (t < K) t = K;
@@ -512,7 +525,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         kcur = A.ekey[qi];
         n_b = A.dnb[qi];
     } else {
-        cur = descend<G, NCH, T, RBV>(Gr, l1, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
+        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
     }
     const int32_t entry0 = cur;
 
@@ -594,7 +607,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (nnew == 0) continue;
         if (fresh) L.Uid[lanes_below(fm)] = nb;
         wave_sync();
-        base_dists<G, NCH, T, RBV>(l1, base, pitch, L.Uid, nnew, qv, L.Uk);
+        base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, L.Uid, nnew, qv, L.Uk);
         wave_sync();
         n_b += nnew;
         // With W full, a new entry not below W's last one cannot enter: keep
@@ -663,21 +676,21 @@ template <typename T, int G>
 constexpr int walk_waves_per_eu() { return sizeof(T) == 4 ? 4 : (G <= 16 ? 5 : 4); }
 template <typename T>
 constexpr int walk_rb_vgprs() { return sizeof(T) == 4 ? 64 : 32; }
-template <int G, int NCH, typename T>
+template <int G, int NCH, typename T, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<T, G>(), 8))) walk_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
         const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (k < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, A.order ? A.order[k] : k, lds);
+        if (k < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2, EXT>(A, A.order ? A.order[k] : k, lds);
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2>(A, qi, lds);
+        walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2, EXT>(A, qi, lds);
         k = fetch_query(A.counter);
     }
 }
@@ -892,7 +905,7 @@ constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32
 // BEAM (1 or 2, equal to A.beam) specialises the fused kernel: with two
 // nodes per step the walk drops new entries that cannot enter a full W before
 // merging; with one the same test measured slower in this larger kernel.
-template <int G, int NCH, typename T, int BEAM>
+template <int G, int NCH, typename T, int BEAM, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T, G>(), 8)))
 search_kernel(SearchArgs A) {
     extern __shared__ char lds_all[];
@@ -904,7 +917,7 @@ search_kernel(SearchArgs A) {
         const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
         const int64_t qi = k < A.nq && A.order ? A.order[k] : k;
         if (k < A.nq) {
-            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0>(A, qi, lds);
+            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0, EXT>(A, qi, lds);
             wave_sync();
             verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         }
@@ -913,7 +926,7 @@ search_kernel(SearchArgs A) {
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0>(A, qi, lds);
+        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0, EXT>(A, qi, lds);
         wave_sync();
         verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         wave_sync();
@@ -929,7 +942,7 @@ search_kernel(SearchArgs A) {
 // Upper-layer rows hold M ids (16 here): 32 VGPRs of rows in flight cover
 // one row of FP32 neighbours at d <= 128 (the keys do not depend on how
 // many rows are in flight), and 6 waves per SIMD keep more descents going.
-template <int G, int NCH, typename T>
+template <int G, int NCH, typename T, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) descend_kernel(SearchArgs A,
                                                                                                   OrderArgs O) {
     extern __shared__ char lds_all[];
@@ -942,7 +955,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     const float p = A.p[qi];
     bool finite = true;
     for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
-    if (query_bad(A, p, A.k[qi], A.ef[qi]) || ballot(!finite) != 0) {
+    if (query_bad<EXT>(A, p, A.k[qi], A.ef[qi]) || ballot(!finite) != 0) {
         if (lane == 0) {
             O.entry[qi] = -1;
             O.ekey[qi] = INFINITY;
@@ -952,18 +965,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
         return;
     }
     const int gsel = (p <= A.cutoff) ? 0 : 1;
-    const bool l1 = gsel == 0;
+    const bool lo = gsel == 0;
     float qv[NCH][4];
     load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
     float kcur;
     int n_b = 0;
-    const int32_t cur = descend<G, NCH, T, 32>(A.g[gsel], l1, reinterpret_cast<const T *>(A.walk_base), A.pitch, qv,
-                                               Uid, Uk, &kcur, &n_b);
+    const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, reinterpret_cast<const T *>(A.walk_base), A.pitch,
+                                                    qv, Uid, Uk, &kcur, &n_b);
     if (lane == 0) {
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;
         O.dnb[qi] = n_b;
-        O.dist[qi] = l1 ? kcur : sqrtf(kcur);
+        // the entry's distance (keys of L2 and L0.5 are its square and root)
+        O.dist[qi] = EXT ? (lo ? kcur * kcur : kcur) : (lo ? kcur : sqrtf(kcur));
     }
 }
 
@@ -1095,15 +1109,22 @@ __global__ void convert_kernel(const float *src, uint16_t *dst, int64_t count, i
 hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s) {
     const dim3 blk(a.waves_per_block * kWave);
     const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
-#define W_LAUNCH(G, NCH)                                                                           \
+#define W_LAUNCH_E(G, NCH, E)                                                                      \
     if (a.storage == UHNSW_STORE_F32)                                                             \
-        hipLaunchKernelGGL((walk_kernel<G, NCH, float>), dim3(grid), blk, lds, s, a);             \
+        hipLaunchKernelGGL((walk_kernel<G, NCH, float, E>), dim3(grid), blk, lds, s, a);          \
     else if (a.storage == UHNSW_STORE_BF16)                                                       \
-        hipLaunchKernelGGL((walk_kernel<G, NCH, bf16_t>), dim3(grid), blk, lds, s, a);            \
+        hipLaunchKernelGGL((walk_kernel<G, NCH, bf16_t, E>), dim3(grid), blk, lds, s, a);         \
     else                                                                                          \
-        hipLaunchKernelGGL((walk_kernel<G, NCH, f16_t>), dim3(grid), blk, lds, s, a);
+        hipLaunchKernelGGL((walk_kernel<G, NCH, f16_t, E>), dim3(grid), blk, lds, s, a);
+#define W_LAUNCH(G, NCH)           \
+    if (a.ext) {                   \
+        W_LAUNCH_E(G, NCH, true)   \
+    } else {                       \
+        W_LAUNCH_E(G, NCH, false)  \
+    }
     UHNSW_LAYOUT_SWITCH(layout, W_LAUNCH)
 #undef W_LAUNCH
+#undef W_LAUNCH_E
     return hipGetLastError();
 }
 
@@ -1119,21 +1140,28 @@ hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t 
 hipError_t launch_search(const SearchArgs &a, int layout, int grid, hipStream_t s) {
     const dim3 blk(a.waves_per_block * kWave);
     const size_t lds = (size_t)a.lds_wave_bytes * a.waves_per_block;
-#define S_LAUNCH_B(G, NCH, B)                                                                     \
+#define S_LAUNCH_B(G, NCH, B, E)                                                                  \
     if (a.storage == UHNSW_STORE_F32)                                                             \
-        hipLaunchKernelGGL((search_kernel<G, NCH, float, B>), dim3(grid), blk, lds, s, a);        \
+        hipLaunchKernelGGL((search_kernel<G, NCH, float, B, E>), dim3(grid), blk, lds, s, a);     \
     else if (a.storage == UHNSW_STORE_BF16)                                                       \
-        hipLaunchKernelGGL((search_kernel<G, NCH, bf16_t, B>), dim3(grid), blk, lds, s, a);       \
+        hipLaunchKernelGGL((search_kernel<G, NCH, bf16_t, B, E>), dim3(grid), blk, lds, s, a);    \
     else                                                                                          \
-        hipLaunchKernelGGL((search_kernel<G, NCH, f16_t, B>), dim3(grid), blk, lds, s, a);
-#define S_LAUNCH(G, NCH)        \
-    if (a.beam == 2) {          \
-        S_LAUNCH_B(G, NCH, 2)   \
-    } else {                    \
-        S_LAUNCH_B(G, NCH, 1)   \
+        hipLaunchKernelGGL((search_kernel<G, NCH, f16_t, B, E>), dim3(grid), blk, lds, s, a);
+#define S_LAUNCH_E(G, NCH, E)      \
+    if (a.beam == 2) {             \
+        S_LAUNCH_B(G, NCH, 2, E)   \
+    } else {                       \
+        S_LAUNCH_B(G, NCH, 1, E)   \
+    }
+#define S_LAUNCH(G, NCH)           \
+    if (a.ext) {                   \
+        S_LAUNCH_E(G, NCH, true)   \
+    } else {                       \
+        S_LAUNCH_E(G, NCH, false)  \
     }
     UHNSW_LAYOUT_SWITCH(layout, S_LAUNCH)
 #undef S_LAUNCH
+#undef S_LAUNCH_E
 #undef S_LAUNCH_B
     return hipGetLastError();
 }
@@ -1143,15 +1171,23 @@ hipError_t launch_order(const SearchArgs &a, const OrderArgs &o, int layout, hip
     const int grid = (int)((a.nq + wpb - 1) / wpb);
     SearchArgs b = a;
     b.waves_per_block = wpb;
-#define D_LAUNCH(G, NCH)                                                                                   \
-    if (a.storage == UHNSW_STORE_F32)                                                                     \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, float>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
-    else if (a.storage == UHNSW_STORE_BF16)                                                               \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, bf16_t>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
-    else                                                                                                  \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, f16_t>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o);
+#define D_LAUNCH_E(G, NCH, E)                                                                                 \
+    if (a.storage == UHNSW_STORE_F32)                                                                        \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, float, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
+    else if (a.storage == UHNSW_STORE_BF16)                                                                  \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, bf16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, \
+                           o);                                                                               \
+    else                                                                                                     \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, f16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o);
+#define D_LAUNCH(G, NCH)           \
+    if (a.ext) {                   \
+        D_LAUNCH_E(G, NCH, true)   \
+    } else {                       \
+        D_LAUNCH_E(G, NCH, false)  \
+    }
     UHNSW_LAYOUT_SWITCH(layout, D_LAUNCH)
 #undef D_LAUNCH
+#undef D_LAUNCH_E
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)((a.nq + 255) / 256);
@@ -1180,33 +1216,35 @@ hipError_t launch_convert(const float *src, void *dst, int64_t count, int storag
 int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits) { return walk_lds_bytes_impl(ef_cap, vis_bits, vis_kbits); }
 int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
 
-// Host stubs of the kernels, by row layout and storage (for occupancy queries).
-#define UHNSW_STUB(NAME, G, NCH, storage)                                            \
-    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&NAME<G, NCH, float>)  \
-     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&NAME<G, NCH, bf16_t>) \
-                                   : reinterpret_cast<const void *>(&NAME<G, NCH, f16_t>))
-#define UHNSW_STUBS(NAME)                                                  \
-    const void *NAME##_ptr(int layout, int storage) {                      \
-        switch (layout) {                                                  \
-            case L8x4x1: return UHNSW_STUB(NAME, 8, 1, storage);           \
-            case L8x4x2: return UHNSW_STUB(NAME, 8, 2, storage);           \
-            case L8x4x4: return UHNSW_STUB(NAME, 8, 4, storage);           \
-            case L16x4x4: return UHNSW_STUB(NAME, 16, 4, storage);         \
-            case L32x4x4: return UHNSW_STUB(NAME, 32, 4, storage);         \
-            default: return UHNSW_STUB(NAME, 64, 4, storage);              \
-        }                                                                  \
+// Host stubs of the walk kernel, by row layout, storage and index variant
+// (for occupancy queries).
+template <bool E>
+const void *walk_stub(int layout, int storage) {
+#define WB(G, NCH)                                                                                   \
+    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&walk_kernel<G, NCH, float, E>)  \
+     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&walk_kernel<G, NCH, bf16_t, E>) \
+                                   : reinterpret_cast<const void *>(&walk_kernel<G, NCH, f16_t, E>))
+    switch (layout) {
+        case L8x4x1: return WB(8, 1);
+        case L8x4x2: return WB(8, 2);
+        case L8x4x4: return WB(8, 4);
+        case L16x4x4: return WB(16, 4);
+        case L32x4x4: return WB(32, 4);
+        default: return WB(64, 4);
     }
-UHNSW_STUBS(walk_kernel)
-#undef UHNSW_STUBS
-#undef UHNSW_STUB
+#undef WB
+}
+const void *walk_kernel_ptr(int layout, int storage, bool ext) {
+    return ext ? walk_stub<true>(layout, storage) : walk_stub<false>(layout, storage);
+}
 
-// The fused kernel's stub by layout, storage and beam width.
-template <int B>
+// The fused kernel's stub by layout, storage, beam width and index variant.
+template <int B, bool E>
 const void *search_stub(int layout, int storage) {
-#define SB(G, NCH)                                                                                       \
-    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&search_kernel<G, NCH, float, B>)  \
-     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&search_kernel<G, NCH, bf16_t, B>) \
-                                   : reinterpret_cast<const void *>(&search_kernel<G, NCH, f16_t, B>))
+#define SB(G, NCH)                                                                                          \
+    (storage == UHNSW_STORE_F32    ? reinterpret_cast<const void *>(&search_kernel<G, NCH, float, B, E>)  \
+     : storage == UHNSW_STORE_BF16 ? reinterpret_cast<const void *>(&search_kernel<G, NCH, bf16_t, B, E>) \
+                                   : reinterpret_cast<const void *>(&search_kernel<G, NCH, f16_t, B, E>))
     switch (layout) {
         case L8x4x1: return SB(8, 1);
         case L8x4x2: return SB(8, 2);
@@ -1217,8 +1255,9 @@ const void *search_stub(int layout, int storage) {
     }
 #undef SB
 }
-const void *search_kernel_ptr(int layout, int storage, int beam) {
-    return beam == 2 ? search_stub<2>(layout, storage) : search_stub<1>(layout, storage);
+const void *search_kernel_ptr(int layout, int storage, int beam, bool ext) {
+    if (ext) return beam == 2 ? search_stub<2, true>(layout, storage) : search_stub<1, true>(layout, storage);
+    return beam == 2 ? search_stub<2, false>(layout, storage) : search_stub<1, false>(layout, storage);
 }
 
 const void *verify_kernel_ptr(int layout) {

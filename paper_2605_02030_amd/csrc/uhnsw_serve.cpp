@@ -62,6 +62,7 @@ struct uhnsw_server {
     uhnsw_ctx *ctx = nullptr;
     uhnsw_serve_config cfg{};
     int d = 0, device = 0, max_batch = 0, slots_total = 0;
+    int variant = 0;  // of the context's index (its p range)
     std::chrono::steady_clock::time_point t0;
     std::vector<float> slot_q;  // slots_total x d
     std::vector<Slot> slot;
@@ -289,6 +290,7 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
     S->ctx = ctx;
     S->cfg = *cfg;
     S->d = uhnsw::ctx_dim(ctx);
+    S->variant = uhnsw::ctx_variant(ctx);
     S->device = uhnsw::ctx_device(ctx);
     // Two lanes by default: one batch runs while the next one gathers
     // arrivals. HIP gives a process four hardware queues by default and the
@@ -330,7 +332,8 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
 
 int uhnsw_serve_submit(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
     if (!S || !q) return UHNSW_EINVAL;
-    if (!(p >= 0.5f && p <= 2.0f) || k < 1 || k > S->cfg.k_max || ef < k || ef > S->cfg.ef_max) return UHNSW_EINVAL;
+    if (!uhnsw::p_in_range(S->variant, p) || k < 1 || k > S->cfg.k_max || ef < k || ef > S->cfg.ef_max)
+        return UHNSW_EINVAL;
     for (int j = 0; j < S->d; ++j)
         if (!std::isfinite(q[j])) return UHNSW_EINVAL;
     {

@@ -19,6 +19,7 @@ UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 2048, 1024
 STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
+VARIANT_STD, VARIANT_EXT = 0, 1
 
 EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
@@ -43,7 +44,8 @@ class uhnsw_graph(ctypes.Structure):
 
 
 class uhnsw_index(ctypes.Structure):
-    _fields_ = [("n", _I64), ("d", _I32), ("base", _P), ("storage", _I32), ("graphs", uhnsw_graph * 2)]
+    _fields_ = [("n", _I64), ("d", _I32), ("base", _P), ("storage", _I32), ("graphs", uhnsw_graph * 2),
+                ("variant", _I32)]
 
 
 class uhnsw_params(ctypes.Structure):
@@ -104,12 +106,13 @@ uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
                          [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
 uhnsw_probe_gather = _sig("uhnsw_probe_gather", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_double)])
 uhnsw_load_graph_files = _sig("uhnsw_load_graph_files", ctypes.c_int,
-                              [_P, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32])
+                              [_P, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, _I32])
 uhnsw_probe_transcendental = _sig("uhnsw_probe_transcendental", ctypes.c_int,
                                   [_P, ctypes.POINTER(ctypes.c_double)])
 uhnsw_check_index = _sig("uhnsw_check_index", ctypes.c_int, [_P, ctypes.c_char_p, _I32])
 uhnsw_check_index_files = _sig("uhnsw_check_index_files", ctypes.c_int,
-                               [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, ctypes.c_char_p, _I32])
+                               [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, _I32, ctypes.c_char_p,
+                                _I32])
 
 
 class UhnswError(RuntimeError):
@@ -154,15 +157,17 @@ def _graph_struct(g, keep):
     return s
 
 
-def index_struct(base, g1, g2, storage: int = STORE_F32):
+def index_struct(base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD):
     """The uhnsw_index for (base, g1, g2) and the arrays it points into (keep
-    them alive while the struct is used)."""
+    them alive while the struct is used). With VARIANT_EXT, g1 / g2 are
+    G_0.5 / G_1."""
     base = np.ascontiguousarray(base, np.float32)
     keep = [base]
     idx = uhnsw_index()
     idx.n, idx.d = base.shape
     idx.base = base.ctypes.data
     idx.storage = storage
+    idx.variant = variant
     idx.graphs[0] = _graph_struct(g1, keep)
     idx.graphs[1] = _graph_struct(g2, keep)
     return idx, keep
@@ -175,10 +180,12 @@ def check_index(idx) -> tuple[int, str]:
     return rc, msg.value.decode()
 
 
-def check_index_files(vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32) -> tuple[int, str]:
+def check_index_files(vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32,
+                      variant: int = VARIANT_STD) -> tuple[int, str]:
     """uhnsw_check_index_files: (return code, reason) with no context or device."""
     msg = ctypes.create_string_buffer(512)
-    rc = uhnsw_check_index_files(vec_path.encode(), g1_path.encode(), g2_path.encode(), storage, msg, len(msg))
+    rc = uhnsw_check_index_files(vec_path.encode(), g1_path.encode(), g2_path.encode(), storage, variant, msg,
+                                 len(msg))
     return rc, msg.value.decode()
 
 
@@ -205,10 +212,11 @@ class Context:
         if rc != UHNSW_OK:
             raise UhnswError(rc, uhnsw_last_error(self.h).decode())
 
-    def load_graphs(self, base, g1, g2, storage: int = STORE_F32) -> None:
+    def load_graphs(self, base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD) -> None:
         """base: (n, d) FP32; g1 / g2: graphs with M, max_level, entry, levels,
-        layers[l].nodes / row_ptr / col (G1 under L1, G2 under L2)."""
-        idx, keep = index_struct(base, g1, g2, storage)
+        layers[l].nodes / row_ptr / col (G1 under L1, G2 under L2; with
+        VARIANT_EXT, G_0.5 under L0.5 and G_1 under L1)."""
+        idx, keep = index_struct(base, g1, g2, storage, variant)
         self._check(uhnsw_load_graphs(self.h, ctypes.byref(idx)))
         self.n, self.d = int(idx.n), int(idx.d)
         del keep
@@ -288,10 +296,11 @@ class Context:
         self._check(uhnsw_device_info(self.h, ctypes.byref(cus), ctypes.byref(khz)))
         return cus.value, khz.value
 
-    def load_graph_files(self, vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32):
+    def load_graph_files(self, vec_path: str, g1_path: str, g2_path: str, storage: int = STORE_F32,
+                         variant: int = VARIANT_STD):
         """Load an index from a .fbin vector file and two UHG1 graph files."""
         self._check(uhnsw_load_graph_files(self.h, os.fsencode(vec_path), os.fsencode(g1_path),
-                                           os.fsencode(g2_path), int(storage)))
+                                           os.fsencode(g2_path), int(storage), int(variant)))
         self.n, self.d = (int(x) for x in np.fromfile(vec_path, np.int32, 2))
 
     def probe_gather(self, row_bytes: int) -> float:

@@ -10,9 +10,17 @@ definition of the U-HNSW paper, Sec. 4.1.2) on the seeded inputs from
   workload 4 (unitgauss-1.18M-d100): every 30th query starting at 1 (the
       K = 10 queries; 334 of 10,000);
   workload 5 at n = 1,000,000 (unitgauss-1M-d96, the serving form's shape
-      at a tenth of its size): every 10th query (200 of 2,000).
+      at a tenth of its size): every 10th query (200 of 2,000);
+  workload 7 (mixture-1M-d128-pext, the extended variant's p over 0.2..1.0):
+      every 10th query (1,000 of 10,000; 10 is coprime to the 9-value grid).
 
-    python tests/golden/make_groundtruth.py [--workload 2|3|4|5] [--threads N]
+    python tests/golden/make_groundtruth.py [--workload 2|3|4|5|7] [--threads N]
+
+With ``--sweep`` it writes tests/golden/gt_sweep_<workload>.npz instead: the
+top-50 of every 50th query of workload 2 (200 queries) under each p of
+SWEEP_P, the paper's 0.1 grid over [0.5, 2] plus its ablation value 0.51
+(Sec. 4.4), each query taking every p (the diagnostics of the parameter
+and ablation sweeps).
 """
 import argparse
 import os
@@ -28,16 +36,39 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SAMPLE = {2: (0, 5), 3: (0, 10), 4: (1, 30), 5: (0, 10)}  # workload -> (first query, stride)
+SAMPLE = {2: (0, 5), 3: (0, 10), 4: (1, 30), 5: (0, 10), 7: (0, 10)}  # workload -> (first query, stride)
 SIZE = {5: 1_000_000}  # workload -> reduced n
 K = 10
+SWEEP_P = np.array([0.5, 0.51] + [round(0.6 + 0.1 * i, 1) for i in range(15)], np.float32)
+SWEEP_K = 50
+
+
+def sweep(a):
+    wl = synth.make_workload(2)
+    qidx = np.arange(0, wl.nq, 50, dtype=np.int32)
+    out = os.path.join(HERE, f"gt_sweep_{wl.name}.npz")
+    t0 = time.time()
+    ids = np.empty((len(SWEEP_P), len(qidx), SWEEP_K), np.int32)
+    S = np.empty((len(SWEEP_P), len(qidx), SWEEP_K), np.float64)
+    for j, pv in enumerate(SWEEP_P):
+        for s in range(0, len(qidx), 50):
+            sel = qidx[s:s + 50]
+            p = np.full(len(sel), pv, np.float32)
+            ids[j, s:s + 50], S[j, s:s + 50] = oracle.bruteforce(wl.base, wl.queries[sel], p, SWEEP_K, a.threads)
+        print(f"p={pv:.2f} done, {time.time() - t0:.0f}s", flush=True)
+    np.savez(out, qidx=qidx, p=SWEEP_P, ids=ids, S=S, K=np.int32(SWEEP_K),
+             digest=np.frombuffer(wl.digest().encode(), np.uint8))
+    print("wrote", out)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--workload", type=int, default=2, choices=sorted(SAMPLE))
+    ap.add_argument("--sweep", action="store_true")
     a = ap.parse_args()
+    if a.sweep:
+        return sweep(a)
     wl = synth.make_workload(a.workload, n=SIZE.get(a.workload))
     first, stride = SAMPLE[a.workload]
     qidx = np.arange(first, wl.nq, stride, dtype=np.int32)

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_default_params(lib):
     p = lib.default_params()
-    assert abs(p.tau - 0.92) < 1e-15 and abs(p.cutoff - 1.4) < 1e-6
+    assert abs(p.tau - 0.92) < 1e-15 and p.cutoff == 0.0  # 0: the index's default cutoff (1.4 / 0.6)
     assert p.beam_width == 1 and p.early_abort == 1 and p.t == 0 and p.kappa == 0
     assert p.fused == 0 and p.persistent == 3 and p.graph == 0 and p.timing == 0
     q = lib.default_params(tau=0.5, beam_width=2)
@@ -51,7 +51,38 @@ def test_struct_sizes_match_header(lib):
     # uhnsw_params: double + float + 11 int32 = 56 bytes
     assert ctypes.sizeof(lib.uhnsw_params) == 56
     assert ctypes.sizeof(lib.uhnsw_graph) == 12 + 4 + 8 + 32 * 8 * 4  # M..entry, pad, level ptr, 4 arrays
+    # n, d (+pad), base, storage (+pad), two graphs, variant (+pad)
+    assert ctypes.sizeof(lib.uhnsw_index) == 8 + 8 + 8 + 8 + 2 * ctypes.sizeof(lib.uhnsw_graph) + 8
     assert lib.STATS_DTYPE.itemsize == 40
+
+
+def test_struct_layouts_match_c(lib, tmp_path):
+    """The ctypes structs against the C compiler's layout of include/uhnsw.h."""
+    import shutil
+    import subprocess
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    fields = {"uhnsw_index": ["n", "d", "base", "storage", "graphs", "variant"],
+              "uhnsw_params": [f for f, _ in lib.uhnsw_params._fields_],
+              "uhnsw_graph": ["M", "max_level", "entry_point", "level", "n_nodes", "nodes", "row_ptr", "col"],
+              "uhnsw_serve_config": [f for f, _ in lib.uhnsw_serve_config._fields_]}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "uhnsw.h"', "int main(void) {"]
+    for st, fl in fields.items():
+        lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fl:
+            lines.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        st, f, v = line.split()
+        cls = getattr(lib, st)
+        got = ctypes.sizeof(cls) if f == "size" else getattr(cls, f).offset
+        assert got == int(v), line
 
 
 def test_null_arguments_rejected_without_device(lib):

@@ -1,0 +1,216 @@
+"""GPU parity of the extended variant (U-HNSW paper, Sec. 4.5): graphs
+G_0.5 (walked under the L0.5 key sum sqrt|x - q|) and G_1, cutoff 0.6,
+p over [0.2, 1]. Same bars as the default pair: C bit-exact against the
+oracle, top-K exact up to the near-tie rule, distances within 1e-5 of FP64,
+for both kernel forms, the schedules, BF16 / FP16 walk storage and serving."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from test_gpu_parity import compare, run_device  # noqa: E402
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx6(torch_cuda, wl6):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    _say("load workload 6 (extended pair)", wl.n, wl.d)
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g05, g1, variant=uhnsw.VARIANT_EXT)
+    yield c
+    c.close()
+
+
+KNOBS = [dict(), dict(fused=1), dict(fused=1, persistent=1), dict(persistent=0), dict(persistent=2),
+         dict(fused=1, beam_width=2), dict(fused=1, persistent=1, graph=1)]
+
+
+@pytest.mark.parametrize("knobs", KNOBS, ids=lambda k: ",".join(f"{a}={b}" for a, b in k.items()) or "default")
+def test_ext_parity(torch_cuda, ctx6, wl6, knobs):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    g, v = ctx6.layout()
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(wl.base)
+    _say("extended parity", knobs)
+    gpu = run_device(torch_cuda, ctx6, wl.queries, wl.p, wl.k, wl.ef, 10, 128, params=uhnsw.default_params(**knobs))
+    compare(wl.base, G05, G1, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, w=knobs.get("beam_width", 1),
+            cutoff=0.6, variant=oracle.VARIANT_EXT)
+    st = gpu[2]
+    assert ((st["graph"] == 1) == (wl.p <= np.float32(0.6))).all()
+    if knobs.get("graph"):  # a replay gives the same bits
+        again = run_device(torch_cuda, ctx6, wl.queries, wl.p, wl.k, wl.ef, 10, 128,
+                           params=uhnsw.default_params(**knobs))
+        for a, b in zip(gpu[:2] + gpu[3:], again[:2] + again[3:]):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_ext_p_edges_and_cutoff(torch_cuda, ctx6, wl6):
+    """p at the ends of [0.2, 1], at the cutoff and one float past it; an
+    explicit cutoff overrides the index's 0.6."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    g, v = ctx6.layout()
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(wl.base)
+    edges = np.array([0.2, 0.5, np.float32(0.6), np.nextafter(np.float32(0.6), np.float32(1)), 1.0], np.float32)
+    p = edges[np.arange(wl.nq) % len(edges)]
+    for cutoff in (0.0, 0.45):
+        gpu = run_device(torch_cuda, ctx6, wl.queries, p, wl.k, wl.ef, 10, 128,
+                         params=uhnsw.default_params(cutoff=cutoff))
+        eff = cutoff or 0.6
+        compare(wl.base, G05, G1, D, wl.queries, p, wl.k, wl.ef, gpu, g, v, cutoff=eff, variant=oracle.VARIANT_EXT)
+        assert ((gpu[2]["graph"] == 1) == (p <= np.float32(eff))).all()
+
+
+def test_ext_p_range(torch_cuda, ctx6, wl6):
+    """The extended index serves p in [0.2, 1]: the host API refuses p
+    outside it, the device path flags such rows and runs the rest."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl6
+    q = wl.queries[:2]
+    k = np.array([10, 10], np.int32)
+    ef = np.array([64, 64], np.int32)
+    for bad in (0.19, 1.01, 1.5, 2.0):
+        with pytest.raises(uhnsw.UhnswError) as e:
+            ctx6.search(q, np.array([bad, 0.5], np.float32), k, ef)
+        assert e.value.code == uhnsw.UHNSW_EINVAL
+    ids, d, st = ctx6.search(q, np.array([0.2, 1.0], np.float32), k, ef)
+    assert (ids >= 0).all() and (st["flags"] == 0).all()
+    p = np.array([0.3, 1.5, 0.1, 0.9], np.float32)
+    ids, dists, st, cid, _ = run_device(torch_cuda, ctx6, wl.queries[:4], p, np.full(4, 10, np.int32),
+                                        np.full(4, 64, np.int32), 10, 64)
+    assert list(st["flags"]) == [0, uhnsw.UHNSW_QBAD, uhnsw.UHNSW_QBAD, 0]
+    assert (ids[[1, 2]] == -1).all() and (ids[[0, 3]] >= 0).all()
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_ext_precision_forms(torch_cuda, wl6, storage):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g05, g1, storage=storage, variant=uhnsw.VARIANT_EXT)
+    g, v = c.layout()
+    G05, G1, D = oracle.Graph(g05), oracle.Graph(g1), oracle.Data(wl.base, storage=storage)
+    for knobs in (dict(), dict(fused=1, persistent=1)):
+        _say("extended storage", storage, knobs)
+        gpu = run_device(torch_cuda, c, wl.queries, wl.p, wl.k, wl.ef, 10, 128,
+                         params=uhnsw.default_params(**knobs))
+        compare(wl.base, G05, G1, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, cutoff=0.6,
+                variant=oracle.VARIANT_EXT)
+    c.close()
+
+
+def test_ext_recall_and_files(torch_cuda, ctx6, wl6, tmp_path):
+    """recall@10 >= 0.9 against the FP64 brute force; the same index loaded
+    from files returns the same bits."""
+    import synth.graphs as sg
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    ids, d, st = ctx6.search(wl.queries, wl.p, wl.k, wl.ef)
+    gt, _ = oracle.bruteforce(wl.base, wl.queries, wl.p, 10)
+    rec = np.mean([len(set(ids[i].tolist()) & set(gt[i].tolist())) / 10 for i in range(wl.nq)])
+    assert rec >= 0.9, rec
+    vp, p1, p2 = (str(tmp_path / f) for f in ("b.fbin", "g05.uhg", "g1.uhg"))
+    sg.save_fbin(vp, wl.base)
+    sg.save_graph_file(p1, g05)
+    sg.save_graph_file(p2, g1)
+    c = uhnsw.Context(0)
+    try:
+        c.load_graph_files(vp, p1, p2, variant=uhnsw.VARIANT_EXT)
+        ids2, d2, _ = c.search(wl.queries, wl.p, wl.k, wl.ef)
+    finally:
+        c.close()
+    np.testing.assert_array_equal(ids, ids2)
+    np.testing.assert_array_equal(d, d2)
+
+
+def test_ext_serving_mix_vs_batch(torch_cuda, ctx6, wl6):
+    """Serving on the extended index: results in a Poisson mix equal the
+    batch search; p outside [0.2, 1] is refused at submit."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl6
+    ids, d, _ = ctx6.search(wl.queries, wl.p, wl.k, wl.ef)
+    srv = uhnsw.Server(ctx6, k_max=10, ef_max=128)
+    try:
+        assert srv.submit(wl.queries[0], 1.5, 10, 64, 999) == uhnsw.UHNSW_EINVAL
+        rng = np.random.Generator(np.random.PCG64(43))
+        arrival = np.cumsum(rng.exponential(1e6 / 100_000, wl.nq))
+        got_ids, got_d, status, _, _, _ = srv.drive(wl.queries, wl.p, wl.k, wl.ef, arrival)
+    finally:
+        srv.stop()
+    assert (status == 0).all()
+    np.testing.assert_array_equal(got_ids[:, :10], ids)
+    np.testing.assert_array_equal(got_d[:, :10], d)
+
+
+def test_reload_recaptures_graphs(torch_cuda, wl1, wl6):
+    """A context that replays captured launch graphs and then loads another
+    index of the same sizes (same buffers, same arguments) must not replay
+    the old capture: its baked arguments name the old graphs and kernel
+    variant. Both the device-pointer and the host-array forms."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl_s, g1, g2 = wl1
+    wl, g05, g1e = wl6
+    assert np.array_equal(wl_s.base, wl.base)
+    p = np.clip(wl.p, 0.5, 1.0).astype(np.float32)  # valid for both variants
+    dev = torch_cuda.device("cuda:0")
+    nq = wl.nq
+    tq = torch_cuda.from_numpy(wl.queries).to(dev)
+    tp = torch_cuda.from_numpy(p).to(dev)
+    tk = torch_cuda.from_numpy(wl.k).to(dev)
+    te = torch_cuda.from_numpy(wl.ef).to(dev)
+    ids = torch_cuda.empty((nq, 10), dtype=torch_cuda.int64, device=dev)
+    dists = torch_cuda.empty((nq, 10), dtype=torch_cuda.float32, device=dev)
+    stats = torch_cuda.zeros((nq, uhnsw.STATS_WORDS), dtype=torch_cuda.int32, device=dev)
+    cid = torch_cuda.empty((nq, 128), dtype=torch_cuda.int32, device=dev)
+    ckey = torch_cuda.empty((nq, 128), dtype=torch_cuda.float32, device=dev)
+    prm = uhnsw.default_params(fused=1, persistent=1, graph=1)
+    c = uhnsw.Context(0)
+    try:
+        results = []
+        for variant, ga, gb in ((uhnsw.VARIANT_STD, g1, g2), (uhnsw.VARIANT_EXT, g05, g1e)):
+            c.load_graphs(wl.base, ga, gb, variant=variant)
+            before = c.graph_captures()
+            for _ in range(2):  # capture, then replay
+                c.search_device(tq, tp, tk, te, 10, 128, ids, dists, stats, cid, ckey, params=prm)
+            torch_cuda.cuda.synchronize()
+            assert c.graph_captures() == before + 1
+            st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(nq)
+            gpu = (ids.cpu().numpy(), dists.cpu().numpy(), st, cid.cpu().numpy(), ckey.cpu().numpy())
+            g, v = c.layout()
+            ext = variant == uhnsw.VARIANT_EXT
+            compare(wl.base, oracle.Graph(ga), oracle.Graph(gb), oracle.Data(wl.base), wl.queries, p, wl.k, wl.ef,
+                    gpu, g, v, cutoff=0.6 if ext else 1.4,
+                    variant=oracle.VARIANT_EXT if ext else oracle.VARIANT_STD)
+            # host-array form with its own captured graph
+            h = [c.search(wl.queries, p, wl.k, wl.ef, params=uhnsw.default_params(graph=1)) for _ in range(2)]
+            np.testing.assert_array_equal(h[0][0], gpu[0])
+            np.testing.assert_array_equal(h[1][0], gpu[0])
+            results.append(gpu[3])
+        assert not np.array_equal(results[0], results[1])  # the walks differ (L0.5 keys below the cutoff)
+    finally:
+        c.close()

@@ -61,10 +61,11 @@ def run_device(torch, ctx, queries, p, k, ef, k_max, ef_max, params=None, c_stri
 
 
 def compare(base, G1, G2, D, queries, p, k, ef, gpu, g, v, w=1, tau=0.92, kappa_param=0, t_param=0,
-            max_excused=0.05):
+            max_excused=0.05, cutoff=1.4, variant=oracle.VARIANT_STD):
     ids, dists, st, cid, ckey = gpu
     nq = len(p)
-    prm = oracle.Params(g=g, v=v, w=w, tau=tau, kappa=kappa_param, t_param=t_param)
+    prm = oracle.Params(g=g, v=v, w=w, tau=tau, kappa=kappa_param, t_param=t_param, cutoff=cutoff,
+                        variant=variant)
     cs = cid.shape[1]
     o = oracle.query_batch(G1, G2, D, queries, p, k, ef, prm, k_stride=ids.shape[1], c_stride=cs)
     ost = o["stats"]
@@ -180,6 +181,26 @@ def test_tau_and_kappa_params(torch_cuda, ctx1, wl1):
         gpu = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64, params=prm)
         compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, tau=tau, kappa_param=kappa,
                 t_param=t)
+
+
+def test_forced_graph_and_sweep_params(torch_cuda, ctx1, wl1):
+    """The settings the method diagnostics use: the walk forced onto one graph
+    by the cutoff, early stop off (tau > 1), and t / tau off their defaults."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    g, v = ctx1.layout()
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    for cutoff, tau, t, graph in ((0.01, 0.92, 0, 2), (3.0, 0.92, 0, 1), (1.4, 1.01, 0, 0), (1.4, 0.75, 30, 0),
+                                  (1.4, 0.95, 45, 0)):
+        prm = uhnsw.default_params(cutoff=cutoff, tau=tau, t=t)
+        gpu = run_device(torch_cuda, ctx1, wl.queries, wl.p, wl.k, wl.ef, 10, 64, params=prm)
+        compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v, tau=tau, t_param=t, cutoff=cutoff)
+        st = gpu[2]
+        if graph:
+            assert (st["graph"] == graph).all()
+        if tau > 1:  # no early stop: every candidate verified
+            assert (st["n_p"] == st["nc"]).all()
 
 
 def test_bad_queries_flagged(torch_cuda, ctx1, wl1):

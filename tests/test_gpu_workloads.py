@@ -41,7 +41,7 @@ def wl2_full():
     return wl, g1, g2
 
 
-def _sample_compare(torch, ctx, wl, g1, g2, ef, params, storage, sample, w=1):
+def _sample_compare(torch, ctx, wl, g1, g2, ef, params, storage, sample, w=1, variant=oracle.VARIANT_STD):
     """All queries on the GPU; the sample compared with the oracle."""
     from paper_2605_02030_amd import uhnsw
 
@@ -51,7 +51,8 @@ def _sample_compare(torch, ctx, wl, g1, g2, ef, params, storage, sample, w=1):
     G1, G2 = oracle.Graph(g1), oracle.Graph(g2)
     D = oracle.Data(wl.base, storage=storage)
     sub = (ids[sample], dists[sample], st[sample], cid[sample], ckey[sample])
-    compare(wl.base, G1, G2, D, wl.queries[sample], wl.p[sample], wl.k[sample], efa[sample], sub, g, v, w=w)
+    compare(wl.base, G1, G2, D, wl.queries[sample], wl.p[sample], wl.k[sample], efa[sample], sub, g, v, w=w,
+            variant=variant, cutoff=0.6 if variant == oracle.VARIANT_EXT else 1.4)
     assert (st["flags"] == 0).all()
     return ids
 
@@ -84,6 +85,42 @@ def test_full_size_bench_configurations(torch_cuda, wl2_full):
     rec2 = np.mean([len(set(got[i].tolist()) & set(gt["ids"][i].tolist())) / 10 for i in range(len(got))])
     _say(f"full-size BF16 batched recall@10 = {rec2:.4f}")
     assert rec2 >= 0.9
+
+
+@pytest.fixture(scope="module")
+def wl7_full():
+    _say("workload 7 full size (extended index): generating inputs and graphs (cached when present)")
+    wl = synth.make_workload(7)
+    g05, g1 = sg.build_graphs(wl, cache=True, verbose=True, extended=True)
+    sys.stdout.flush()
+    return wl, g05, g1
+
+
+EF_EXT = 256
+
+
+@pytest.mark.timeout(1200)
+def test_full_size_extended(torch_cuda, wl7_full):
+    """The extended index (G_0.5 + G_1, p over 0.2..1.0) on the benchmark's
+    vectors in the launch configurations bench.py --workload 7 times."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl7_full
+    gt = dict(np.load(os.path.join(ROOT, "tests", "golden", f"gt_{wl.name}.npz")))
+    assert bytes(gt["digest"]).decode() == wl.digest()
+    sample = np.arange(5, wl.nq, 211)  # 48 queries, all 9 p values
+    for storage, prm, w in ((uhnsw.STORE_F32, None, 1),
+                            (uhnsw.STORE_BF16, uhnsw.default_params(fused=1, persistent=1, beam_width=2,
+                                                                    visited_slots=1024), 2)):
+        ctx = uhnsw.Context(0)
+        ctx.load_graphs(wl.base, g05, g1, storage=storage, variant=uhnsw.VARIANT_EXT)
+        ids = _sample_compare(torch_cuda, ctx, wl, g05, g1, EF_EXT, prm, storage, sample, w=w,
+                              variant=oracle.VARIANT_EXT)
+        ctx.close()
+        got = ids[gt["qidx"], :10]
+        rec = np.mean([len(set(got[i].tolist()) & set(gt["ids"][i].tolist())) / 10 for i in range(len(got))])
+        _say(f"full-size extended storage={storage} recall@10 = {rec:.4f}")
+        assert rec >= 0.9
 
 
 @pytest.fixture(scope="module")

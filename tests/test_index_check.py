@@ -119,6 +119,12 @@ def test_base_and_sizes_refused(lib, small):
     assert _check(lib, bad, g1, g2)[0] == lib.UHNSW_EINVAL
     rc, msg = _check(lib, wl.base, g1, g2, storage=3)
     assert rc == lib.UHNSW_EINVAL and "storage" in msg
+    idx, keep = lib.index_struct(wl.base, g1, g2, variant=2)
+    rc, msg = lib.check_index(idx)
+    assert rc == lib.UHNSW_EINVAL and "variant" in msg
+    idx.variant = lib.VARIANT_EXT  # any structurally valid pair is accepted for either variant
+    assert lib.check_index(idx) == (lib.UHNSW_OK, "")
+    del keep
     wide = np.zeros((wl.n, lib.UHNSW_DMAX + 1), np.float32)
     rc, msg = _check(lib, wide, g1, g2)
     assert rc == lib.UHNSW_EINVAL and "d=" in msg
