@@ -14,6 +14,11 @@ truth on a 2,000-query sample) reaches 0.9; it is chosen before timing.
 
 Prints one JSON line. ``value`` is the plain FP32 form's QPS; the
 BF16-storage + persistent-batched form is reported beside it in ``forms``.
+
+Other legs: ``--workload 3 | 4 | 5`` (precision, batching and serving forms
+on their own inputs), ``--workload 7`` (the same vectors and queries on the
+extended index of the paper's Sec. 4.5, p over 0.2..1.0, efSearch from
+{128, 256, 384, 512}) and ``--sweep`` (method diagnostics).
 """
 from __future__ import annotations
 
@@ -41,6 +46,9 @@ TRAFFIC = {"kernel_sha256_prefix": "519663a13a082add", "ef": 256, "bytes_per_lau
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
+# the extended index's p near 0.2 needs a wider walk (oracle recall@10 at
+# ef 256 / 512: 0.89 / 0.95 on workload 7)
+EF_GRID_EXT = (128, 256, 384, 512)
 # workload -> n actually used: the serving form's 10M-row graphs are not built
 # here (about an hour of CPU per graph pair), a 1M-row index of the same
 # distribution stands in for it
@@ -122,10 +130,10 @@ def torch_int32(torch):
     return torch.int32
 
 
-def calibrate(form, gt, log_prefix):
+def calibrate(form, gt, log_prefix, grid=EF_GRID):
     torch = form.torch
     chosen, table = None, []
-    for ef in EF_GRID:
+    for ef in grid:
         form.set_ef(ef)
         form.step()
         form.step()
@@ -553,7 +561,7 @@ def main():
             f.set_ef(a.ef)
             ef, table = a.ef, []
         else:
-            ef, table = calibrate(f, gt, name)
+            ef, table = calibrate(f, gt, name, EF_GRID_EXT if ext else EF_GRID)
         r = timed(f, a.steps, a.warmup, wl, rate_khz)
         rec = recall_at_k(f.ids.cpu().numpy(), gt["ids"], gt["qidx"])
         qps = wl.nq * a.steps / r["total_s"]
