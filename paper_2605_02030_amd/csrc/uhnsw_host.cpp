@@ -70,6 +70,7 @@ struct uhnsw_ctx {
     int64_t n = 0;
     int32_t d = 0, storage = 0, layout = 0;
     int32_t variant = UHNSW_VARIANT_STD;
+    bool l05_fast = false;  // every base value 0 or of magnitude >= 2^-72
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
     GraphDev g[2];
@@ -583,6 +584,11 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     c->d = idx->d;
     c->storage = idx->storage;
     c->variant = idx->variant;
+    c->l05_fast = true;
+    for (int64_t i = 0; i < n * idx->d && c->l05_fast; ++i) {
+        const float v = std::fabs(idx->base[i]);
+        c->l05_fast = v == 0.0f || v >= 0x1p-72f;
+    }
     c->layout = layout;
     c->pitch = pitch;
     c->loaded = true;
@@ -699,6 +705,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     // Sec. 3.1's 1.4, or Sec. 4.5's 0.6 for the extended pair
     a.cutoff = prm.cutoff > 0.0f ? prm.cutoff : (c->variant == UHNSW_VARIANT_EXT ? 0.6f : 1.4f);
     a.ext = c->variant == UHNSW_VARIANT_EXT;
+    a.l05_fast = c->l05_fast;
     a.t_param = prm.t;
     a.kappa_param = prm.kappa;
     a.beam = prm.beam_width;

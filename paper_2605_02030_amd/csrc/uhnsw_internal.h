@@ -79,6 +79,9 @@ struct SearchArgs {
     // index variant: 0 = G1 (L1) / G2 (L2), 1 = G_0.5 (L0.5) / G_1 (L1);
     // picks the kernel instantiation, read on the host only
     int32_t ext;
+    // every base value is 0 or at least 2^-72 in magnitude (the extended
+    // walk may then take the short correctly rounded root)
+    int32_t l05_fast;
 };
 
 // Cost-ordered launch: a pre-pass descends every query and orders the

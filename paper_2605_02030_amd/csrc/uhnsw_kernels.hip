@@ -120,7 +120,27 @@ struct Elem<f16_t> {
 // L0.5 distance is its square; the extended index of Sec. 4.5 walks G_0.5
 // under it). Each lane sums its elements in ascending order, then the lane
 // group combines pairwise.
-constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3;
+// kMetL05F: the same key when every nonzero |x - q| is at least 2^-95 (the
+// host and the query checks guarantee it), rooted by sqrt_rn_large.
+constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3, kMetL05F = 4;
+
+// Magnitude at or above which a nonzero base or query value keeps every
+// nonzero difference with another such value (or with 0) at or above
+// 2^-95: the difference is a multiple of the smaller operand's ulp.
+constexpr float kL05FastMin = 0x1p-72f;
+
+// Square root rounded to nearest for x = 0, +inf or x >= 2^-96. The
+// hardware root r is within one ulp of the true root, so the rounded root is
+// r - ulp, r or r + ulp; the signs of the residuals x - (r - ulp) r and
+// x - (r + ulp) r, each exact in sign through one fused multiply-add (no
+// underflow at these magnitudes), pick it.
+__device__ __forceinline__ float sqrt_rn_large(float x) {
+    const float r = __builtin_amdgcn_sqrtf(x);
+    const float rm = __uint_as_float(__float_as_uint(r) - 1u);
+    const float rp = __uint_as_float(__float_as_uint(r) + 1u);
+    const float y = __builtin_fmaf(-rm, r, x) <= 0.0f ? rm : r;
+    return __builtin_fmaf(-rp, r, x) > 0.0f ? rp : y;
+}
 
 // keys[r] = delta(row ids[r], q) for r < nrows. All lanes must call. The
 // loads of up to RB row-steps are issued before any arithmetic so that a
@@ -163,6 +183,8 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
                         s = s + fabsf(dlt);
                     else if (MET == kMetL2)
                         s = __builtin_fmaf(dlt, dlt, s);
+                    else if (MET == kMetL05F)
+                        s = s + sqrt_rn_large(fabsf(dlt));
                     else
                         s = s + sqrtf(fabsf(dlt));  // correctly rounded root
                 }
@@ -175,11 +197,14 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
 }
 
 // lo: the query walks graph 0 (G1, or G_0.5 when EXT) rather than graph 1
-// (G2, or G_1 when EXT).
+// (G2, or G_1 when EXT). fast (EXT only): the L0.5 roots may take the short
+// correctly rounded form (no nonzero |x - q| below 2^-95).
 template <int G, int NCH, typename T, int RBV, bool EXT>
-__device__ __forceinline__ void base_dists(bool lo, const T *base, int64_t pitch, const int32_t *ids, int nrows,
-                                           const float (&qv)[NCH][4], float *keys) {
-    if (lo)
+__device__ __forceinline__ void base_dists(bool lo, bool fast, const T *base, int64_t pitch, const int32_t *ids,
+                                           int nrows, const float (&qv)[NCH][4], float *keys) {
+    if (EXT && lo && fast)
+        rows_base_dist<G, NCH, T, kMetL05F, RBV>(base, pitch, ids, nrows, qv, keys);
+    else if (lo)
         rows_base_dist<G, NCH, T, EXT ? kMetL05 : kMetL1, RBV>(base, pitch, ids, nrows, qv, keys);
     else
         rows_base_dist<G, NCH, T, EXT ? kMetL1 : kMetL2, RBV>(base, pitch, ids, nrows, qv, keys);
@@ -423,13 +448,13 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
 // entry node and its key, and adds the base distances computed to *n_b.
 // Uid / Uk: 64-entry LDS scratch of the wave.
 template <int G, int NCH, typename T, int RBV, bool EXT>
-__device__ int32_t descend(const DevGraph &Gr, bool lo, const T *base, int64_t pitch, const float (&qv)[NCH][4],
-                           int32_t *Uid, float *Uk, float *kout, int *n_b) {
+__device__ int32_t descend(const DevGraph &Gr, bool lo, bool fast, const T *base, int64_t pitch,
+                           const float (&qv)[NCH][4], int32_t *Uid, float *Uk, float *kout, int *n_b) {
     const int lane = lane_id();
     int32_t cur = Gr.entry;
     if (lane == 0) Uid[0] = cur;
     wave_sync();
-    base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, Uid, 1, qv, Uk);
+    base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, Uid, 1, qv, Uk);
     wave_sync();
     float kcur = Uk[0];
     *n_b += 1;
@@ -441,7 +466,7 @@ __device__ int32_t descend(const DevGraph &Gr, bool lo, const T *base, int64_t p
             const int cnt = popc64(ballot(nb >= 0));
             if (nb >= 0) Uid[lane] = nb;  // valid ids come first in each row
             wave_sync();
-            base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, Uid, cnt, qv, Uk);
+            base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, Uid, cnt, qv, Uk);
             wave_sync();
             *n_b += cnt;
             float kb = lane < cnt ? Uk[lane] : INFINITY;
@@ -484,9 +509,14 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     uhnsw_stats *st = A.stats + qi;
     int32_t *cid = A.cand_ids ? A.cand_ids + qi * A.c_stride : nullptr;
     float *ckey = A.cand_keys ? A.cand_keys + qi * A.c_stride : nullptr;
-    bool finite = true;
-    for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
+    bool finite = true, tiny = false;
+    for (int j = lane; j < A.d; j += kWave) {
+        const float v = A.queries[qi * A.d + j];
+        finite = finite && isfinite(v);
+        if (EXT) tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+    }
     const bool bad = query_bad<EXT>(A, p, K, ef) || ballot(!finite) != 0;
+    const bool fast = EXT && A.l05_fast && ballot(tiny) == 0;
     if (bad) {
         if (cid)
             for (int i = lane; i < A.c_stride; i += kWave) {
@@ -525,7 +555,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         kcur = A.ekey[qi];
         n_b = A.dnb[qi];
     } else {
-        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
+        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, fast, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
     }
     const int32_t entry0 = cur;
 
@@ -607,7 +637,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (nnew == 0) continue;
         if (fresh) L.Uid[lanes_below(fm)] = nb;
         wave_sync();
-        base_dists<G, NCH, T, RBV, EXT>(lo, base, pitch, L.Uid, nnew, qv, L.Uk);
+        base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, L.Uid, nnew, qv, L.Uk);
         wave_sync();
         n_b += nnew;
         // With W full, a new entry not below W's last one cannot enter: keep
@@ -953,8 +983,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
     if (qi >= A.nq) return;
     const float p = A.p[qi];
-    bool finite = true;
-    for (int j = lane; j < A.d; j += kWave) finite = finite && isfinite(A.queries[qi * A.d + j]);
+    bool finite = true, tiny = false;
+    for (int j = lane; j < A.d; j += kWave) {
+        const float v = A.queries[qi * A.d + j];
+        finite = finite && isfinite(v);
+        if (EXT) tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+    }
+    const bool fast = EXT && A.l05_fast && ballot(tiny) == 0;
     if (query_bad<EXT>(A, p, A.k[qi], A.ef[qi]) || ballot(!finite) != 0) {
         if (lane == 0) {
             O.entry[qi] = -1;
@@ -970,8 +1005,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
     float kcur;
     int n_b = 0;
-    const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, reinterpret_cast<const T *>(A.walk_base), A.pitch,
-                                                    qv, Uid, Uk, &kcur, &n_b);
+    const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, fast, reinterpret_cast<const T *>(A.walk_base),
+                                                    A.pitch, qv, Uid, Uk, &kcur, &n_b);
     if (lane == 0) {
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;

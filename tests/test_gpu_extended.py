@@ -214,3 +214,38 @@ def test_reload_recaptures_graphs(torch_cuda, wl1, wl6):
         assert not np.array_equal(results[0], results[1])  # the walks differ (L0.5 keys below the cutoff)
     finally:
         c.close()
+
+
+def test_ext_tiny_values_exact(torch_cuda, wl6):
+    """The L0.5 walk's two root forms give the same bits as the oracle's
+    correctly rounded sqrtf. First an index with tiny values in one
+    coordinate (multiples of 1e-30, so differences there fall below 2^-96
+    where the short form could underflow: the whole index takes the long
+    form), with queries tiny in the same coordinate; then an ordinary index
+    with every other query carrying one tiny coordinate (those queries take
+    the long form, the rest the short one). The other coordinates keep S_p
+    at ordinary magnitudes."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g05, g1 = wl6
+    tiny = np.float32(1e-30)
+    base_t = wl.base.copy()
+    base_t[:, 5] = tiny * (np.arange(wl.n) % 7).astype(np.float32)
+    q_t = wl.queries.copy()
+    q_t[:, 5] = tiny * (np.arange(wl.nq) % 5).astype(np.float32)
+    q_half = wl.queries.copy()
+    q_half[::2, 3] = tiny
+    for name, base, queries in (("tiny coordinate in the index", base_t, q_t),
+                                ("tiny coordinate in half the queries", wl.base, q_half)):
+        _say("extended exact roots:", name)
+        c = uhnsw.Context(0)
+        try:
+            c.load_graphs(base, g05, g1, variant=uhnsw.VARIANT_EXT)
+            g, v = c.layout()
+            for knobs in (dict(), dict(fused=1, persistent=1)):
+                gpu = run_device(torch_cuda, c, queries, wl.p, wl.k, wl.ef, 10, 128,
+                                 params=uhnsw.default_params(**knobs))
+                compare(base, oracle.Graph(g05), oracle.Graph(g1), oracle.Data(base), queries, wl.p, wl.k, wl.ef,
+                        gpu, g, v, cutoff=0.6, variant=oracle.VARIANT_EXT)
+        finally:
+            c.close()
