@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of the walk kernel from two rocprofv3 counter passes
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source and ef.
-TRAFFIC = {"kernel_sha256_prefix": "b2e4e33ff3be18e5", "ef": 256, "bytes_per_launch": 27.416e9}
+TRAFFIC = {"kernel_sha256_prefix": "913ffb50c27d1261", "ef": 256, "bytes_per_launch": 27.417e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
