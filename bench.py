@@ -391,7 +391,11 @@ def run_sweep(a, torch, uhnsw, sg, synth):
           default tau, tau in 0.75..0.95 at t = 300; ef = 500, K = 50, p
           spread over the 0.1 grid;
       cutoff: recall at each p with the walk forced onto G1 or G2 (the
-          crossover the graph-choice cutoff of Sec. 3.1 rests on).
+          crossover the graph-choice cutoff of Sec. 3.1 rests on);
+      per_p_hnsw: at p = 0.5, U-HNSW (G1 + verification) against HNSW on a
+          graph built for that p (G_0.5 of the extended index, walked under
+          L0.5), efSearch swept (the comparison of Sec. 4.3, Fig. 4, where
+          the walk computes the p's metric exactly).
     One JSON line."""
     wl = synth.make_workload(2)
     gt = dict(np.load(SWEEP_GT_PATH))
@@ -404,7 +408,7 @@ def run_sweep(a, torch, uhnsw, sg, synth):
     nq = wl.nq
     qidx, grid, gt_ids = gt["qidx"], gt["p"], gt["ids"]
     grid16 = [float(v) for v in grid if abs(float(v) - 0.51) > 1e-6]
-    KM, EFM = 50, 500
+    KM, EFM = 50, 512
     q = torch.from_numpy(wl.queries).to(dev)
     ids = torch.empty((nq, KM), dtype=torch.int64, device=dev)
     dists = torch.empty((nq, KM), dtype=torch.float32, device=dev)
@@ -417,7 +421,7 @@ def run_sweep(a, torch, uhnsw, sg, synth):
         assert abs(float(grid[j]) - float(pv)) < 1e-6
         return gt_ids[j, s]
 
-    def run(p_all, K, ef, steps=10, **kw):
+    def run(p_all, K, ef, steps=10, ctx=ctx, **kw):
         tp = torch.from_numpy(np.ascontiguousarray(p_all, np.float32)).to(dev)
         tk = torch.full((nq,), K, dtype=torch.int32, device=dev)
         te = torch.full((nq,), ef, dtype=torch.int32, device=dev)
@@ -481,6 +485,19 @@ def run_sweep(a, torch, uhnsw, sg, synth):
             row[name] = dict(recall_at_10=r["recall"], qps=r["qps"])
         out["cutoff"].append(row)
         log("cutoff", json.dumps(row))
+    g05, _ = sg.build_graphs(wl, cache=True, verbose=True, extended=True)
+    ctx_e = uhnsw.Context(0)
+    ctx_e.load_graphs(wl.base, g05, g1, variant=uhnsw.VARIANT_EXT)
+    out["per_p_hnsw"] = []
+    p_all = np.full(nq, 0.5, np.float32)
+    for name, c in (("U-HNSW: G1 + verification", ctx), ("HNSW on G_0.5 (L0.5 walk)", ctx_e)):
+        for ef in (64, 128, 192, 256, 384, 512):
+            r = run(p_all, 10, ef, ctx=c)
+            row = dict(p=0.5, method=name, ef=ef, recall_at_10=r["recall"], qps=r["qps"], walk_ms=r["walk_ms"],
+                       verify_ms=r["verify_ms"], mean_n_p=r["mean_n_p"])
+            out["per_p_hnsw"].append(row)
+            log("per-p", json.dumps(row))
+    ctx_e.close()
     ctx.close()
     print(json.dumps(out), flush=True)
 
