@@ -41,9 +41,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # HBM traffic of the walk kernel from two rocprofv3 counter passes
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
-# + WRITE_SIZE x 1.0 per launch, valid only for that kernel source and ef.
-TRAFFIC = {"kernel_sha256_prefix": "913ffb50c27d1261", "ef": 256, "bytes_per_launch": 27.417e9}
+# + WRITE_SIZE x 1.0 per launch, valid only for that kernel source, the host
+# code that plans its launch (cache size, block shape) and ef.
+TRAFFIC = {"kernel_sha256_prefix": "913ffb50c27d1261", "host_sha256_prefix": "958a2c90fce6b820", "ef": 256,
+           "bytes_per_launch": 25.010e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
+HOST_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_host.cpp")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
 # the extended index's p near 0.2 needs a wider walk (oracle recall@10 at
@@ -603,6 +606,8 @@ def main():
 
     with open(KERNEL_SRC, "rb") as fh:
         kernel_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(HOST_SRC, "rb") as fh:
+        host_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
     main_name = "fp32" if "fp32" in forms else next(iter(forms))
     m = forms[main_name]
     ef_main, r_main, ach_main = chosen_fp32 if chosen_fp32 else (m["ef"], None, m["walk_gbs"])
@@ -629,7 +634,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(ach_main, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach_main / HBM_PEAK_GBS, 4),
                      "traffic": (TRAFFIC["bytes_per_launch"] if kernel_hash == TRAFFIC["kernel_sha256_prefix"]
-                                 and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" and not ext else None),
+                                 and host_hash == TRAFFIC["host_sha256_prefix"] and m["ef"] == TRAFFIC["ef"]
+                                 and main_name == "fp32" and not ext else None),
                      "kernel": "walk_kernel", "walk_ms": m["walk_ms"]},
         "probes": probes,
         "forms": forms,

@@ -103,8 +103,11 @@ typedef struct {
     int32_t kappa;            /* batch size; 0 -> max(K, 2)                   */
     int32_t beam_width;       /* nodes expanded per walk step, 1 = HNSW       */
     int32_t early_abort;      /* exact partial-sum abort in verification      */
-    int32_t visited_slots;    /* LDS visited-cache slots; 0 -> automatic      */
-    int32_t waves_per_block;  /* 0 -> automatic                               */
+    int32_t visited_slots;    /* LDS visited-cache slots; 0 -> the largest
+                                 power of two in 1,024 .. 8,192 that keeps a
+                                 wave's LDS within 12 KiB (8,192 above ef
+                                 512)                                        */
+    int32_t waves_per_block;  /* 0 -> 1                                       */
     int32_t persistent;       /* schedule of the queries over the waves:
                                  0: one wave per query by grid position;
                                  1: persistent launch, waves take queries
@@ -166,7 +169,7 @@ const char *uhnsw_last_error(const uhnsw_ctx *ctx);
  * Errors: EINVAL (any structural violation: id out of range, degree above
  * 2M / M, neighbour not on the layer, entry point not on the top layer,
  * d > UHNSW_DMAX, M0 > 64, a non-finite base value, an unknown variant),
- * ENOMEM, EDEVICE. */
+ * ESTATE (a server is running on the context), ENOMEM, EDEVICE. */
 int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
 
 /* uhnsw_load_graphs from files (host paths):
@@ -316,7 +319,9 @@ typedef struct {
 
 void uhnsw_serve_default_config(uhnsw_serve_config *cfg);
 
-/* Start a server on a context with a loaded index.
+/* Start a server on a context with a loaded index. Until uhnsw_serve_stop
+ * the server's thread searches on the context: the caller makes no other
+ * call on it, and uhnsw_load_graphs refuses with ESTATE.
  * Errors: EINVAL (limits), ESTATE (no index), ENOMEM, EBUSY (hbm_budget
  * below one query per stream). */
 int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out);

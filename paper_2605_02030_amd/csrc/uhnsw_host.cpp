@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -70,6 +71,7 @@ struct uhnsw_ctx {
     int64_t n = 0;
     int32_t d = 0, storage = 0, layout = 0;
     int32_t variant = UHNSW_VARIANT_STD;
+    std::atomic<int> servers{0};  // uhnsw_serve_start .. uhnsw_serve_stop
     bool l05_fast = false;  // every base value 0 or of magnitude >= 2^-72
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
@@ -122,6 +124,7 @@ bool p_in_range(int variant, float p) {
     return variant == UHNSW_VARIANT_EXT ? (p >= 0.2f && p <= 1.0f) : (p >= 0.5f && p <= 2.0f);
 }
 int ctx_variant(const uhnsw_ctx *c) { return c->variant; }
+void ctx_servers(uhnsw_ctx *c, int delta) { c->servers += delta; }
 int ctx_dim(const uhnsw_ctx *c) { return c->d; }
 int ctx_device(const uhnsw_ctx *c) { return c->device; }
 }  // namespace uhnsw
@@ -257,17 +260,39 @@ struct Plan {
 
 int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan *pl) {
     pl->ef_cap = round_up(std::max(ef_max, 1), 4);
+    // cache geometry for a slot count: log2 slots, and the key width when
+    // 16-bit quotient slots suffice for the id range (see VisCache), else 0
+    auto vis_geometry = [c](int slots, int *bits, int *kbits) {
+        int b = 0;
+        while ((1 << b) < slots) ++b;
+        int kb = 1;
+        while (kb < 31 && ((int64_t)1 << kb) < c->n) ++kb;
+        if (kb < b + 1) kb = b + 1;
+        *bits = b;
+        *kbits = (kb - b <= 15) ? kb : 0;
+    };
     int slots = prm.visited_slots;
-    if (slots <= 0) slots = ef_max <= 256 ? 2048 : ef_max <= 512 ? 4096 : 8192;
-    int bits = 0;
-    while ((1 << bits) < slots) ++bits;
+    if (slots <= 0 && ef_max > 512) {
+        slots = 8192;
+    } else if (slots <= 0) {
+        // The largest cache that keeps a wave's LDS within 12 KiB (13 waves
+        // per CU). A larger cache forgets fewer nodes (fewer repeated
+        // distances), a smaller one leaves room for more waves; measured on
+        // the 1M x 128 workload: at ef 256, 4,096 slots (11.5 KiB) beat
+        // 2,048 by 4 %; at ef 384 and 512, 4,096 slots would leave 11-12
+        // waves per CU and 2,048 wins by 16 % and 41 %.
+        constexpr int kLdsWaveBudget = 12 * 1024;
+        for (slots = 8192; slots > 1024; slots /= 2) {
+            int b, kb;
+            vis_geometry(slots, &b, &kb);
+            if (walk_lds_bytes(pl->ef_cap, b, kb) <= kLdsWaveBudget) break;
+        }
+    }
+    int bits = 0, kbits = 0;
+    vis_geometry(slots, &bits, &kbits);
     if (bits < 6 || bits > 14) return fail(c, UHNSW_EINVAL, "visited_slots %d outside [64, 16384]", slots);
     pl->vis_bits = bits;
-    // 16-bit quotient slots when the id width allows (see VisCache)
-    int kbits = 1;
-    while (kbits < 31 && ((int64_t)1 << kbits) < c->n) ++kbits;
-    if (kbits < bits + 1) kbits = bits + 1;
-    pl->vis_kbits = (kbits - bits <= 15) ? kbits : 0;
+    pl->vis_kbits = kbits;
     const int kappa_max = prm.kappa > 0 ? prm.kappa : std::max(k_max, 2);
     pl->kv_cap = round_up(std::max(k_max, kappa_max), 4);
     pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits, pl->vis_kbits);
@@ -275,7 +300,10 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     // fused kernel: the verification's arrays follow the walk's list W
     pl->search_bytes = std::max(pl->walk_bytes, pl->ef_cap * 8 + pl->verify_bytes);
     const int per_wave = prm.fused ? pl->search_bytes : std::max(pl->walk_bytes, pl->verify_bytes);
-    pl->wpb = prm.waves_per_block > 0 ? prm.waves_per_block : std::max(1, std::min(4, 65536 / per_wave));
+    // one wave per block by default: LDS is granted per block, and single-
+    // wave blocks pack a CU's 160 KiB without leftovers (at 11.5 KiB per
+    // wave, four-wave blocks fit 3 per CU, 12 waves; one-wave blocks 13)
+    pl->wpb = prm.waves_per_block > 0 ? prm.waves_per_block : 1;
     if (pl->wpb > 4) return fail(c, UHNSW_EINVAL, "waves_per_block %d > 4", pl->wpb);
     if ((size_t)per_wave * pl->wpb > 64 * 1024)
         return fail(c, UHNSW_EUNSUPPORTED, "LDS plan %d B/wave x %d waves exceeds 64 KiB per block", per_wave,
@@ -540,6 +568,7 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     if (!c) return UHNSW_EINVAL;
     int r0 = check_index(&c->err, idx);
     if (r0) return r0;
+    if (c->servers.load() > 0) return fail(c, UHNSW_ESTATE, "a server is running on this context");
     HIP_OR_FAIL(c, hipSetDevice(c->device));
     // Searches still in flight read the buffers about to be replaced, and
     // captured launch graphs hold the old index's pointers, sizes and kernel

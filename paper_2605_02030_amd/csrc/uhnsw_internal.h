@@ -122,6 +122,7 @@ const void *verify_kernel_ptr(int layout);
 const void *search_kernel_ptr(int layout, int storage, int beam, bool ext);
 int ctx_dim(const uhnsw_ctx *c);
 int ctx_variant(const uhnsw_ctx *c);
+void ctx_servers(uhnsw_ctx *c, int delta);  // servers running on the context
 bool p_in_range(int variant, float p);  // the index variant's p range
 int ctx_device(const uhnsw_ctx *c);
 

@@ -325,6 +325,7 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
             return UHNSW_ENOMEM;
         }
     S->t0 = std::chrono::steady_clock::now();
+    uhnsw::ctx_servers(ctx, +1);  // the index may not be replaced while this server runs
     S->th = std::thread(dispatcher, S);
     *out = S;
     return UHNSW_OK;
@@ -389,6 +390,7 @@ int uhnsw_serve_stop(uhnsw_server *S) {
     if (S->th.joinable()) S->th.join();
     const int rc = S->error.load();
     for (auto &L : S->lanes) free_lane(L);
+    uhnsw::ctx_servers(S->ctx, -1);
     delete S;
     return rc;
 }

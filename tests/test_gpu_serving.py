@@ -105,3 +105,31 @@ def test_admission_busy_and_budget(torch_cuda, ctxs, wl1):
     with pytest.raises(uhnsw.UhnswError) as e:
         uhnsw.Server(ctxs, k_max=100, ef_max=128, hbm_budget=64)
     assert e.value.code == uhnsw.UHNSW_EBUSY
+
+
+def test_reload_refused_while_serving(torch_cuda, wl1):
+    """The server's thread searches on the context: replacing the index under
+    it is refused until the server stops."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    c = uhnsw.Context(0)
+    try:
+        c.load_graphs(wl.base, g1, g2)
+        srv = uhnsw.Server(c, k_max=10, ef_max=64)
+        try:
+            with pytest.raises(uhnsw.UhnswError) as e:
+                c.load_graphs(wl.base, g1, g2)
+            assert e.value.code == uhnsw.UHNSW_ESTATE
+            assert srv.submit(wl.queries[0], float(wl.p[0]), 10, 64, 7) == uhnsw.UHNSW_OK
+            got = []
+            while not got:
+                got = srv.poll()
+            assert got[0].tag == 7 and got[0].status == 0
+        finally:
+            srv.stop()
+        c.load_graphs(wl.base, g1, g2)  # allowed again
+        ids, _, _ = c.search(wl.queries[:1], wl.p[:1], wl.k[:1], wl.ef[:1])
+        assert (ids >= 0).all()
+    finally:
+        c.close()
