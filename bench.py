@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source, the host
 # code that plans its launch (cache size, block shape) and ef.
-TRAFFIC = {"kernel_sha256_prefix": "913ffb50c27d1261", "host_sha256_prefix": "958a2c90fce6b820", "ef": 256,
+TRAFFIC = {"kernel_sha256_prefix": "f421f9320bb0d904", "host_sha256_prefix": "958a2c90fce6b820", "ef": 256,
            "bytes_per_launch": 25.010e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 HOST_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_host.cpp")
