@@ -72,7 +72,8 @@ struct uhnsw_ctx {
     int32_t d = 0, storage = 0, layout = 0;
     int32_t variant = UHNSW_VARIANT_STD;
     std::atomic<int> servers{0};  // uhnsw_serve_start .. uhnsw_serve_stop
-    bool l05_fast = false;  // every base value 0 or of magnitude >= 2^-72
+    bool l05_fast = false;   // every base value 0 or of magnitude >= 2^-72
+    bool l05_table = false;  // every base value an integer in [0, 255]
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
     GraphDev g[2];
@@ -285,7 +286,7 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
         for (slots = 8192; slots > 1024; slots /= 2) {
             int b, kb;
             vis_geometry(slots, &b, &kb);
-            if (walk_lds_bytes(pl->ef_cap, b, kb) <= kLdsWaveBudget) break;
+            if (walk_lds_bytes(pl->ef_cap, b, kb, c->variant == UHNSW_VARIANT_EXT) <= kLdsWaveBudget) break;
         }
     }
     int bits = 0, kbits = 0;
@@ -295,7 +296,7 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     pl->vis_kbits = kbits;
     const int kappa_max = prm.kappa > 0 ? prm.kappa : std::max(k_max, 2);
     pl->kv_cap = round_up(std::max(k_max, kappa_max), 4);
-    pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits, pl->vis_kbits);
+    pl->walk_bytes = walk_lds_bytes(pl->ef_cap, pl->vis_bits, pl->vis_kbits, c->variant == UHNSW_VARIANT_EXT);
     pl->verify_bytes = verify_lds_bytes(pl->kv_cap);
     // fused kernel: the verification's arrays follow the walk's list W
     pl->search_bytes = std::max(pl->walk_bytes, pl->ef_cap * 8 + pl->verify_bytes);
@@ -613,10 +614,11 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     c->d = idx->d;
     c->storage = idx->storage;
     c->variant = idx->variant;
-    c->l05_fast = true;
-    for (int64_t i = 0; i < n * idx->d && c->l05_fast; ++i) {
-        const float v = std::fabs(idx->base[i]);
-        c->l05_fast = v == 0.0f || v >= 0x1p-72f;
+    c->l05_fast = c->l05_table = true;
+    for (int64_t i = 0; i < n * idx->d && (c->l05_fast || c->l05_table); ++i) {
+        const float v = idx->base[i];
+        c->l05_fast = c->l05_fast && (v == 0.0f || std::fabs(v) >= 0x1p-72f);
+        c->l05_table = c->l05_table && v >= 0.0f && v <= 255.0f && v == std::rint(v);
     }
     c->layout = layout;
     c->pitch = pitch;
@@ -735,6 +737,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     a.cutoff = prm.cutoff > 0.0f ? prm.cutoff : (c->variant == UHNSW_VARIANT_EXT ? 0.6f : 1.4f);
     a.ext = c->variant == UHNSW_VARIANT_EXT;
     a.l05_fast = c->l05_fast;
+    a.l05_table = c->l05_table;
     a.t_param = prm.t;
     a.kappa_param = prm.kappa;
     a.beam = prm.beam_width;

@@ -82,6 +82,9 @@ struct SearchArgs {
     // every base value is 0 or at least 2^-72 in magnitude (the extended
     // walk may then take the short correctly rounded root)
     int32_t l05_fast;
+    // every base value is an integer in [0, 255] (the extended walk may then
+    // read its roots from a table)
+    int32_t l05_table;
 };
 
 // Cost-ordered launch: a pre-pass descends every query and orders the
@@ -115,7 +118,7 @@ hipError_t launch_gather_probe(const float *base, int64_t n, int64_t pitch, int 
                                uint32_t seed, float *sink, hipStream_t s);
 hipError_t launch_trans_probe(int blocks, int iters, float *sink, hipStream_t s);
 hipError_t launch_convert(const float *src, void *dst, int64_t count, int storage, hipStream_t s);
-int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits);
+int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits, bool ext);
 int verify_lds_bytes(int kv_cap);
 const void *walk_kernel_ptr(int layout, int storage, bool ext);
 const void *verify_kernel_ptr(int layout);

@@ -122,7 +122,14 @@ struct Elem<f16_t> {
 // group combines pairwise.
 // kMetL05F: the same key when every nonzero |x - q| is at least 2^-95 (the
 // host and the query checks guarantee it), rooted by sqrt_rn_large.
-constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3, kMetL05F = 4;
+// kMetL05T: the same key when every value is an integer in [0, 255] (so is
+// |x - q|): the roots come from a 256-entry table of sqrtf(i) in LDS.
+constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3, kMetL05F = 4, kMetL05T = 5;
+// how the L0.5 roots are taken for a query (see above)
+constexpr int kRootSqrtf = 0, kRootShort = 1, kRootTable = 2;
+constexpr int kRootTableBytes = 256 * 4;
+// descent pre-pass LDS per wave: 64 ids + 64 keys (+ the root table)
+__host__ __device__ constexpr int descend_lds_wave_bytes(bool ext) { return 512 + (ext ? kRootTableBytes : 0); }
 
 // Magnitude at or above which a nonzero base or query value keeps every
 // nonzero difference with another such value (or with 0) at or above
@@ -148,7 +155,7 @@ __device__ __forceinline__ float sqrt_rn_large(float x) {
 template <int G, int NCH, typename T, int MET, int RBV>
 __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64_t pitch,
                                                const int32_t *ids, int nrows, const float (&qv)[NCH][4],
-                                               float *keys) {
+                                               float *keys, const float *sqt = nullptr) {
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
     constexpr int RB = (RBV * 4 / (NCH * V * (int)sizeof(T))) > 0 ? (RBV * 4 / (NCH * V * (int)sizeof(T))) : 1;
@@ -185,6 +192,8 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
                         s = __builtin_fmaf(dlt, dlt, s);
                     else if (MET == kMetL05F)
                         s = s + sqrt_rn_large(fabsf(dlt));
+                    else if (MET == kMetL05T)
+                        s = s + sqt[(int)fabsf(dlt)];
                     else
                         s = s + sqrtf(fabsf(dlt));  // correctly rounded root
                 }
@@ -197,12 +206,15 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
 }
 
 // lo: the query walks graph 0 (G1, or G_0.5 when EXT) rather than graph 1
-// (G2, or G_1 when EXT). fast (EXT only): the L0.5 roots may take the short
-// correctly rounded form (no nonzero |x - q| below 2^-95).
+// (G2, or G_1 when EXT). root (EXT only): how the L0.5 roots are taken,
+// kRootTable reading sqt (LDS), kRootShort the short correctly rounded form.
 template <int G, int NCH, typename T, int RBV, bool EXT>
-__device__ __forceinline__ void base_dists(bool lo, bool fast, const T *base, int64_t pitch, const int32_t *ids,
-                                           int nrows, const float (&qv)[NCH][4], float *keys) {
-    if (EXT && lo && fast)
+__device__ __forceinline__ void base_dists(bool lo, int root, const float *sqt, const T *base, int64_t pitch,
+                                           const int32_t *ids, int nrows, const float (&qv)[NCH][4],
+                                           float *keys) {
+    if (EXT && lo && root == kRootTable)
+        rows_base_dist<G, NCH, T, kMetL05T, RBV>(base, pitch, ids, nrows, qv, keys, sqt);
+    else if (EXT && lo && root == kRootShort)
         rows_base_dist<G, NCH, T, kMetL05F, RBV>(base, pitch, ids, nrows, qv, keys);
     else if (lo)
         rows_base_dist<G, NCH, T, EXT ? kMetL05 : kMetL1, RBV>(base, pitch, ids, nrows, qv, keys);
@@ -410,14 +422,16 @@ struct WalkLds {
     int32_t *Uid;
     float *Uk;
     int32_t *Ulo, *Urank, *Slo;
+    float *sqt;
 };
 
 __host__ __device__ inline int vis_bytes_impl(int vis_bits, int vis_kbits) {
     return (1 << vis_bits) * (vis_kbits ? 2 : 4);
 }
 
-__host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits, int vis_kbits) {
-    return ef_cap * 8 + vis_bytes_impl(vis_bits, vis_kbits) + kUCap * 4 * 5;
+// ext: the extended index's walk also holds the L0.5 root table
+__host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits, int vis_kbits, bool ext) {
+    return ef_cap * 8 + vis_bytes_impl(vis_bits, vis_kbits) + kUCap * 4 * 5 + (ext ? kRootTableBytes : 0);
 }
 
 __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kbits) {
@@ -432,6 +446,7 @@ __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kb
     L.Ulo = reinterpret_cast<int32_t *>(L.Uk + kUCap);
     L.Urank = L.Ulo + kUCap;
     L.Slo = L.Urank + kUCap;
+    L.sqt = reinterpret_cast<float *>(L.Slo + kUCap);  // extended walk only
     return L;
 }
 
@@ -443,18 +458,35 @@ __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, i
     return !p_ok || K < 1 || K > A.k_max || K > UHNSW_KMAX || ef < K || ef > A.ef_max || ef > A.ef_cap;
 }
 
+// An integer in [0, 255]: with every base value such too (checked on the
+// host), each |x - q| indexes the root table exactly.
+__device__ __forceinline__ bool is_byte_value(float v) { return v >= 0.0f && v <= 255.0f && v == rintf(v); }
+
+// The L0.5 root form of one query (wave-uniform inputs): the table when the
+// index and the query hold byte values (the table is filled here: 256
+// correctly rounded roots), else the short form when no difference can fall
+// below 2^-95, else sqrtf.
+__device__ __forceinline__ int l05_root_mode(const SearchArgs &A, bool no_tiny, bool bytes, float *sqt) {
+    if (A.l05_table && bytes) {
+        for (int i = lane_id(); i < 256; i += kWave) sqt[i] = sqrtf((float)i);
+        wave_sync();
+        return kRootTable;
+    }
+    return A.l05_fast && no_tiny ? kRootShort : kRootSqrtf;
+}
+
 // Greedy descent over layers max_level .. 1 of graph Gr from its entry
 // point, always to the smallest (key, id) neighbour; returns the layer-0
 // entry node and its key, and adds the base distances computed to *n_b.
 // Uid / Uk: 64-entry LDS scratch of the wave.
 template <int G, int NCH, typename T, int RBV, bool EXT>
-__device__ int32_t descend(const DevGraph &Gr, bool lo, bool fast, const T *base, int64_t pitch,
+__device__ int32_t descend(const DevGraph &Gr, bool lo, int root, const float *sqt, const T *base, int64_t pitch,
                            const float (&qv)[NCH][4], int32_t *Uid, float *Uk, float *kout, int *n_b) {
     const int lane = lane_id();
     int32_t cur = Gr.entry;
     if (lane == 0) Uid[0] = cur;
     wave_sync();
-    base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, Uid, 1, qv, Uk);
+    base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, 1, qv, Uk);
     wave_sync();
     float kcur = Uk[0];
     *n_b += 1;
@@ -466,7 +498,7 @@ __device__ int32_t descend(const DevGraph &Gr, bool lo, bool fast, const T *base
             const int cnt = popc64(ballot(nb >= 0));
             if (nb >= 0) Uid[lane] = nb;  // valid ids come first in each row
             wave_sync();
-            base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, Uid, cnt, qv, Uk);
+            base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, cnt, qv, Uk);
             wave_sync();
             *n_b += cnt;
             float kb = lane < cnt ? Uk[lane] : INFINITY;
@@ -509,14 +541,17 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     uhnsw_stats *st = A.stats + qi;
     int32_t *cid = A.cand_ids ? A.cand_ids + qi * A.c_stride : nullptr;
     float *ckey = A.cand_keys ? A.cand_keys + qi * A.c_stride : nullptr;
-    bool finite = true, tiny = false;
+    bool finite = true, tiny = false, byte = true;
     for (int j = lane; j < A.d; j += kWave) {
         const float v = A.queries[qi * A.d + j];
         finite = finite && isfinite(v);
-        if (EXT) tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+        if (EXT) {
+            tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+            byte = byte && is_byte_value(v);
+        }
     }
     const bool bad = query_bad<EXT>(A, p, K, ef) || ballot(!finite) != 0;
-    const bool fast = EXT && A.l05_fast && ballot(tiny) == 0;
+    const int root = EXT ? l05_root_mode(A, ballot(tiny) == 0, ballot(!byte) == 0, L.sqt) : kRootSqrtf;
     if (bad) {
         if (cid)
             for (int i = lane; i < A.c_stride; i += kWave) {
@@ -555,7 +590,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         kcur = A.ekey[qi];
         n_b = A.dnb[qi];
     } else {
-        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, fast, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
+        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, root, L.sqt, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
     }
     const int32_t entry0 = cur;
 
@@ -637,7 +672,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (nnew == 0) continue;
         if (fresh) L.Uid[lanes_below(fm)] = nb;
         wave_sync();
-        base_dists<G, NCH, T, RBV, EXT>(lo, fast, base, pitch, L.Uid, nnew, qv, L.Uk);
+        base_dists<G, NCH, T, RBV, EXT>(lo, root, L.sqt, base, pitch, L.Uid, nnew, qv, L.Uk);
         wave_sync();
         n_b += nnew;
         // With W full, a new entry not below W's last one cannot enter: keep
@@ -989,18 +1024,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     extern __shared__ char lds_all[];
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
-    int32_t *Uid = reinterpret_cast<int32_t *>(lds_all + (size_t)wave * 512);
-    float *Uk = reinterpret_cast<float *>(lds_all + (size_t)wave * 512 + 256);
+    constexpr int kWaveBytes = descend_lds_wave_bytes(EXT);
+    int32_t *Uid = reinterpret_cast<int32_t *>(lds_all + (size_t)wave * kWaveBytes);
+    float *Uk = reinterpret_cast<float *>(lds_all + (size_t)wave * kWaveBytes + 256);
+    float *sqt = reinterpret_cast<float *>(lds_all + (size_t)wave * kWaveBytes + 512);  // EXT only
     const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
     if (qi >= A.nq) return;
     const float p = A.p[qi];
-    bool finite = true, tiny = false;
+    bool finite = true, tiny = false, byte = true;
     for (int j = lane; j < A.d; j += kWave) {
         const float v = A.queries[qi * A.d + j];
         finite = finite && isfinite(v);
-        if (EXT) tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+        if (EXT) {
+            tiny = tiny || (v != 0.0f && fabsf(v) < kL05FastMin);
+            byte = byte && is_byte_value(v);
+        }
     }
-    const bool fast = EXT && A.l05_fast && ballot(tiny) == 0;
     if (query_bad<EXT>(A, p, A.k[qi], A.ef[qi]) || ballot(!finite) != 0) {
         if (lane == 0) {
             O.entry[qi] = -1;
@@ -1016,8 +1055,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     load_query<G, NCH>(A.queries + qi * A.d, A.d, qv);
     float kcur;
     int n_b = 0;
-    const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, fast, reinterpret_cast<const T *>(A.walk_base),
-                                                    A.pitch, qv, Uid, Uk, &kcur, &n_b);
+    const int root = EXT ? l05_root_mode(A, ballot(tiny) == 0, ballot(!byte) == 0, sqt) : kRootSqrtf;
+    const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, root, sqt,
+                                                    reinterpret_cast<const T *>(A.walk_base), A.pitch, qv, Uid, Uk,
+                                                    &kcur, &n_b);
     if (lane == 0) {
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;
@@ -1219,12 +1260,12 @@ hipError_t launch_order(const SearchArgs &a, const OrderArgs &o, int layout, hip
     b.waves_per_block = wpb;
 #define D_LAUNCH_E(G, NCH, E)                                                                                 \
     if (a.storage == UHNSW_STORE_F32)                                                                        \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, float, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o); \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, float, E>), dim3(grid), dim3(wpb * kWave), wpb * descend_lds_wave_bytes(E), s, b, o); \
     else if (a.storage == UHNSW_STORE_BF16)                                                                  \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, bf16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, \
+        hipLaunchKernelGGL((descend_kernel<G, NCH, bf16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * descend_lds_wave_bytes(E), s, b, \
                            o);                                                                               \
     else                                                                                                     \
-        hipLaunchKernelGGL((descend_kernel<G, NCH, f16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * 512, s, b, o);
+        hipLaunchKernelGGL((descend_kernel<G, NCH, f16_t, E>), dim3(grid), dim3(wpb * kWave), wpb * descend_lds_wave_bytes(E), s, b, o);
 #define D_LAUNCH(G, NCH)           \
     if (a.ext) {                   \
         D_LAUNCH_E(G, NCH, true)   \
@@ -1259,7 +1300,9 @@ hipError_t launch_convert(const float *src, void *dst, int64_t count, int storag
     return hipGetLastError();
 }
 
-int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits) { return walk_lds_bytes_impl(ef_cap, vis_bits, vis_kbits); }
+int walk_lds_bytes(int ef_cap, int vis_bits, int vis_kbits, bool ext) {
+    return walk_lds_bytes_impl(ef_cap, vis_bits, vis_kbits, ext);
+}
 int verify_lds_bytes(int kv_cap) { return verify_lds_bytes_impl(kv_cap); }
 
 // Host stubs of the walk kernel, by row layout, storage and index variant

@@ -249,3 +249,33 @@ def test_ext_tiny_values_exact(torch_cuda, wl6):
                         gpu, g, v, cutoff=0.6, variant=oracle.VARIANT_EXT)
         finally:
             c.close()
+
+
+def test_ext_byte_values_table(torch_cuda, wl6):
+    """Byte-valued inputs (integers in [0, 255], as SIFT's): the extended walk
+    reads its L0.5 roots from a table; C stays bit-exact with the oracle's
+    sqrtf. Queries with a non-integer or out-of-range coordinate fall back
+    to the computed root per query, in the same launch."""
+    import synth.graphs as sg
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, _ = wl6
+    base = np.rint(np.clip(wl.base * 40.0 + 128.0, 0, 255)).astype(np.float32)
+    queries = np.rint(np.clip(wl.queries * 40.0 + 128.0, 0, 255)).astype(np.float32)
+    queries[1::4, 2] += np.float32(0.5)       # not an integer
+    queries[2::4, 7] = np.float32(-3.0)       # below the table
+    g05 = sg.build_graph(base, sg.METRIC_L05, M=16, ef_construction=100, seed=3, cache=False)
+    g1 = sg.build_graph(base, sg.METRIC_L1, M=16, ef_construction=100, seed=3, cache=False)
+    for storage in (uhnsw.STORE_F32, uhnsw.STORE_BF16):
+        c = uhnsw.Context(0)
+        try:
+            c.load_graphs(base, g05, g1, storage=storage, variant=uhnsw.VARIANT_EXT)
+            g, v = c.layout()
+            for knobs in (dict(), dict(fused=1, persistent=1), dict(persistent=0)):
+                _say("extended byte table", storage, knobs)
+                gpu = run_device(torch_cuda, c, queries, wl.p, wl.k, wl.ef, 10, 128,
+                                 params=uhnsw.default_params(**knobs))
+                compare(base, oracle.Graph(g05), oracle.Graph(g1), oracle.Data(base, storage=storage), queries,
+                        wl.p, wl.k, wl.ef, gpu, g, v, cutoff=0.6, variant=oracle.VARIANT_EXT)
+        finally:
+            c.close()
