@@ -133,6 +133,20 @@ def torch_int32(torch):
     return torch.int32
 
 
+def host_api_qps(form, wl, ef, uhnsw, calls=5):
+    """uhnsw_search (host arrays in and out, copies over PCIe inside the
+    call, launch sequence replayed as one hipGraph): queries per second of
+    wall time per call. Reported beside ``value``, never as it."""
+    efa = np.full(wl.nq, ef, np.int32)
+    prm = uhnsw.default_params(graph=1)
+    for _ in range(2):
+        form.ctx.search(wl.queries, wl.p, wl.k, efa, params=prm)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        form.ctx.search(wl.queries, wl.p, wl.k, efa, params=prm)
+    return round(wl.nq * calls / (time.perf_counter() - t0), 1)
+
+
 def calibrate(form, gt, log_prefix, grid=EF_GRID):
     torch = form.torch
     chosen, table = None, []
@@ -595,6 +609,8 @@ def main():
         if f.pipeline > 1:  # walk_ms / walk_gbs: one launch alone; step_gbs: per step with overlap
             forms[name].update(streams=f.pipeline,
                                step_gbs=round(r["walk_bytes"] / (r["total_s"] / a.steps) / 1e9, 1))
+        if name == "fp32":  # the host-pointer entry point: PCIe copies in and out included
+            forms[name]["host_api_qps"] = host_api_qps(f, wl, ef, uhnsw)
         log(name, json.dumps(forms[name]))
         if name == "fp32":
             chosen_fp32 = (ef, r, achieved)
