@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source, the host
 # code that plans its launch (cache size, block shape) and ef.
-TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "e7a38bb9da2cc58e", "ef": 256,
+TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "bfaedbccf65914b7", "ef": 256,
            "bytes_per_launch": 25.011e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 HOST_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_host.cpp")
@@ -528,6 +528,8 @@ def main():
     ap.add_argument("--forms", default="fp32,bf16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-host-api", action="store_true",
+                    help="skip the host-pointer (PCIe-inclusive) leg of the FP32 form")
     ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5, 7),
                     help="2: the headline workload; 3: precision form; 4: batching form; "
                          "5: serving form (n = 1,000,000 of its 10,000,000); 7: the headline vectors on "
@@ -609,7 +611,10 @@ def main():
         if f.pipeline > 1:  # walk_ms / walk_gbs: one launch alone; step_gbs: per step with overlap
             forms[name].update(streams=f.pipeline,
                                step_gbs=round(r["walk_bytes"] / (r["total_s"] / a.steps) / 1e9, 1))
-        if name == "fp32":  # the host-pointer entry point: PCIe copies in and out included
+        # the host-pointer entry point (PCIe copies in and out included); left
+        # out of --copy-probe runs, whose 1 GiB copies must be the only large
+        # copy dispatches the counter scaling reads, and of --no-host-api runs
+        if name == "fp32" and not a.copy_probe and not a.no_host_api:
             forms[name]["host_api_qps"] = host_api_qps(f, wl, ef, uhnsw)
         log(name, json.dumps(forms[name]))
         if name == "fp32":

@@ -234,15 +234,16 @@ int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const 
 
 /* Batching form: pick execution knobs for this index and query mix by
  * timing the search on the given device queries (same arrays and limits as
- * uhnsw_search_device): visited-cache slots, waves per block, persistent or
- * not, and -- only with UHNSW_TUNE_BEAM in `flags`, since it changes the
+ * uhnsw_search_device): visited-cache slots, waves per block, the schedule
+ * (persistent field), for a persistent winner the resident waves per CU
+ * (8, 12 or as many as fit), and -- only with UHNSW_TUNE_BEAM in `flags`, since it changes the
  * walk's trajectory -- the beam width. Every other knob leaves results
  * unchanged. With UHNSW_TUNE_PIPELINED the knobs are timed as back-to-back
  * launches alternating between `stream` and a second stream of the
  * context (the throughput of a caller that keeps two batches in flight)
  * instead of one launch at a time. *prm is read for Algorithm 1's
  * parameters and receives the chosen knobs. Results are cached per (n, d,
- * storage, ef range, k_max, flags, fused) in the context.
+ * storage, ef range, k_max, flags, fused, index variant) in the context.
  * Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
 #define UHNSW_TUNE_BEAM 1
 #define UHNSW_TUNE_PIPELINED 2

@@ -1018,7 +1018,7 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
     const uint64_t key = ((uint64_t)c->n << 20) ^ ((uint64_t)c->d << 8) ^ ((uint64_t)c->storage << 4) ^
                          ((uint64_t)(ef_max <= 64 ? 0 : ef_max <= 128 ? 1 : ef_max <= 256 ? 2 : 3) << 40) ^
                          ((uint64_t)k_max << 44) ^ ((uint64_t)(flags & 3) << 58) ^
-                         ((uint64_t)(prm->fused != 0) << 61);
+                         ((uint64_t)(prm->fused != 0) << 61) ^ ((uint64_t)c->variant << 62);
     const bool allow_beam = (flags & UHNSW_TUNE_BEAM) != 0;
     const bool pipelined = (flags & UHNSW_TUNE_PIPELINED) != 0;
     for (auto &e : c->tuned)
@@ -1048,6 +1048,52 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
     hipStream_t st2[2] = {s, s == c->stream ? c->tune_stream : c->stream};
     uhnsw_params best = *prm;
     float best_ms = 1e30f;
+    // median of three timed runs (after one untimed) of the knobs in t;
+    // returns 1 when the shape does not fit (skipped), 0 or an error code
+    auto measure = [&](uhnsw_params t, float *median_ms) -> int {
+        t.graph = 0;
+        t.timing = 1;
+        float ms[3];
+        for (int rep = -1; rep < 3; ++rep) {
+            if (pipelined) {  // 6 launches, two in flight: wall time per launch
+                t.timing = 0;
+                if (rep >= 0) HIP_OR_FAIL(c, hipStreamSynchronize(s));
+                const auto t0 = std::chrono::steady_clock::now();
+                for (int l = 0; l < 6; ++l) {
+                    const int j = l & 1;
+                    int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
+                                                 oid[j].as<int64_t>(), od[j].as<float>(), os[j].as<uhnsw_stats>(),
+                                                 nullptr, nullptr, 0, st2[j]);
+                    if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
+                        c->err.clear();
+                        HIP_OR_FAIL(c, hipStreamSynchronize(st2[0]));
+                        HIP_OR_FAIL(c, hipStreamSynchronize(st2[1]));
+                        return 1;
+                    }
+                    if (rc) return rc;
+                }
+                HIP_OR_FAIL(c, hipStreamSynchronize(st2[0]));
+                HIP_OR_FAIL(c, hipStreamSynchronize(st2[1]));
+                const double dt =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                if (rep >= 0) ms[rep] = (float)(dt / 6);
+                continue;
+            }
+            int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max, oid[0].as<int64_t>(),
+                                         od[0].as<float>(), os[0].as<uhnsw_stats>(), nullptr, nullptr, 0, s);
+            if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
+                c->err.clear();  // this shape does not fit: skip it
+                return 1;
+            }
+            if (rc) return rc;
+            float w = 0, v = 0;
+            if ((rc = uhnsw_last_timing(c, &w, &v))) return rc;
+            if (rep >= 0) ms[rep] = w + v;
+        }
+        std::sort(ms, ms + 3);
+        *median_ms = ms[1];
+        return 0;
+    };
     const int slots_c[] = {1024, 2048, 4096};
     const int wpb_c[] = {1, 2, 4};
     for (int beam = 1; beam <= (allow_beam ? 2 : 1); ++beam)
@@ -1060,54 +1106,30 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
                     t.waves_per_block = wpb;
                     t.persistent = pers;
                     t.waves_per_cu = 0;
-                    t.graph = 0;
-                    t.timing = 1;
-                    float ms[3];
-                    bool ok = true;
-                    for (int rep = -1; rep < 3 && ok; ++rep) {
-                        if (pipelined) {  // 6 launches, two in flight: wall time per launch
-                            t.timing = 0;
-                            if (rep >= 0) HIP_OR_FAIL(c, hipStreamSynchronize(s));
-                            const auto t0 = std::chrono::steady_clock::now();
-                            for (int l = 0; l < 6 && ok; ++l) {
-                                const int j = l & 1;
-                                int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
-                                                             oid[j].as<int64_t>(), od[j].as<float>(),
-                                                             os[j].as<uhnsw_stats>(), nullptr, nullptr, 0, st2[j]);
-                                if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
-                                    ok = false;
-                                    c->err.clear();
-                                } else if (rc) {
-                                    return rc;
-                                }
-                            }
-                            HIP_OR_FAIL(c, hipStreamSynchronize(st2[0]));
-                            HIP_OR_FAIL(c, hipStreamSynchronize(st2[1]));
-                            const double dt = std::chrono::duration<double, std::milli>(
-                                                  std::chrono::steady_clock::now() - t0).count();
-                            if (rep >= 0) ms[rep] = (float)(dt / 6);
-                            continue;
-                        }
-                        int rc = uhnsw_search_device(c, queries, nq, p, k, ef, k_max, ef_max, &t, k_max,
-                                                     oid[0].as<int64_t>(), od[0].as<float>(), os[0].as<uhnsw_stats>(),
-                                                     nullptr, nullptr, 0, s);
-                        if (rc == UHNSW_EUNSUPPORTED || rc == UHNSW_EINVAL) {
-                            ok = false;  // this shape does not fit: skip it
-                            c->err.clear();
-                            break;
-                        }
-                        if (rc) return rc;
-                        float w = 0, v = 0;
-                        if ((rc = uhnsw_last_timing(c, &w, &v))) return rc;
-                        if (rep >= 0) ms[rep] = w + v;
-                    }
-                    if (!ok) continue;
-                    std::sort(ms, ms + 3);
-                    if (ms[1] < best_ms) {
-                        best_ms = ms[1];
+                    float ms = 0.0f;
+                    const int r = measure(t, &ms);
+                    if (r < 0) return r;
+                    if (r == 0 && ms < best_ms) {
+                        best_ms = ms;
                         best = t;
                     }
                 }
+    // queries per CU: a persistent launch may do better with fewer resident
+    // waves than fit (less contention for the caches and HBM queues)
+    if (best.persistent == 1 || best.persistent == 2) {
+        const uhnsw_params base = best;
+        for (int wcu : {8, 12}) {
+            uhnsw_params t = base;
+            t.waves_per_cu = wcu;
+            float ms = 0.0f;
+            const int r = measure(t, &ms);
+            if (r < 0) return r;
+            if (r == 0 && ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    }
     best.timing = prm->timing;
     best.graph = prm->graph;
     c->tuned.emplace_back(key, best);
