@@ -13,7 +13,8 @@ verification (Algorithm 1 of the U-HNSW paper). efSearch is the smallest of
 truth on a 2,000-query sample) reaches 0.9; it is chosen before timing.
 
 Prints one JSON line. ``value`` is the plain FP32 form's QPS; the
-BF16-storage + persistent-batched form is reported beside it in ``forms``.
+BF16-storage batched form and the same batching on FP32 rows are reported
+beside it in ``forms``.
 
 Other legs: ``--workload 3 | 4 | 5`` (precision, batching and serving forms
 on their own inputs), ``--workload 7`` (the same vectors and queries on the
@@ -525,7 +526,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ef", type=int, default=0, help="skip calibration, use this efSearch")
-    ap.add_argument("--forms", default="fp32,bf16-batched")
+    ap.add_argument("--forms", default="fp32,bf16-batched,fp32-batched",
+                    help="comma list of fp32, bf16-batched, fp32-batched, fp16-batched")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-host-api", action="store_true",
@@ -580,7 +582,8 @@ def main():
         del src, dst
 
     forms = {}
-    specs = {"fp32": (uhnsw.STORE_F32, 0, 4), "bf16-batched": (uhnsw.STORE_BF16, 1, 2)}
+    specs = {"fp32": (uhnsw.STORE_F32, 0, 4), "bf16-batched": (uhnsw.STORE_BF16, 1, 2),
+             "fp32-batched": (uhnsw.STORE_F32, 1, 4), "fp16-batched": (uhnsw.STORE_F16, 1, 2)}
     chosen_fp32 = None
     probes = None
     for name in [f.strip() for f in a.forms.split(",") if f.strip()]:
