@@ -543,7 +543,7 @@ def main():
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the query path runs on a single MI355X and this build has no "
+        print("bench.py measures one GPU: the query path runs on a single MI355X and the library has no "
               "multi-GPU path (replicate the index per GPU and shard queries to scale).", file=sys.stderr)
         sys.exit(2)
 

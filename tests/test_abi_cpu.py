@@ -24,7 +24,7 @@ def lib():
     return uhnsw
 
 
-def test_header_declares_north_star_entry_points():
+def test_header_declares_load_and_search_entry_points():
     names = _declared()
     for must in ("uhnsw_load_graphs", "uhnsw_search", "uhnsw_search_device", "uhnsw_create", "uhnsw_destroy",
                  "uhnsw_last_error"):
