@@ -155,7 +155,10 @@ void uhnsw_default_params(uhnsw_params *prm);
  * Errors: EINVAL (out NULL, no such device), EDEVICE, ENOMEM. */
 int uhnsw_create(int device, uhnsw_ctx **out);
 
-/* Free the context and all device memory it owns. NULL is a no-op. */
+/* Free the context and all device memory it owns. NULL is a no-op. With a
+ * server still running on the context (uhnsw_serve_start without
+ * uhnsw_serve_stop) nothing is freed and uhnsw_last_error says so: stop the
+ * servers first. */
 void uhnsw_destroy(uhnsw_ctx *ctx);
 
 /* Message for the last failure on ctx (or of uhnsw_create when ctx is NULL).

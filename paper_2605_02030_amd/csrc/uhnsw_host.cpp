@@ -533,6 +533,10 @@ int uhnsw_create(int device, uhnsw_ctx **out) {
 
 void uhnsw_destroy(uhnsw_ctx *c) {
     if (!c) return;
+    if (c->servers.load() > 0) {  // a server's thread still searches on it: keep it alive
+        c->err = "uhnsw_destroy refused: a server is running on this context";
+        return;
+    }
     (void)hipSetDevice(c->device);
     // Wait for every search of this context: the caller's streams may already
     // be gone, so the device is synchronised rather than each stream.

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -201,6 +202,9 @@ class Context:
         self.n = self.d = 0
 
     def close(self, _destroy=uhnsw_destroy):  # bound early: usable during interpreter shutdown
+        """Stop the servers still running on this context, then free it."""
+        for srv in list(getattr(self, "_servers", ())):
+            srv.stop()
         if getattr(self, "h", None):
             _destroy(self.h)
             self.h = None
@@ -337,6 +341,9 @@ class Server:
         if rc != UHNSW_OK:
             raise UhnswError(rc, "uhnsw_serve_start failed")
         self.h, self.ctx, self.d, self.cfg = h, ctx, ctx.d, c
+        if not hasattr(ctx, "_servers"):
+            ctx._servers = weakref.WeakSet()
+        ctx._servers.add(self)
 
     def submit(self, q, p, k, ef, tag) -> int:
         q = np.ascontiguousarray(q, np.float32)

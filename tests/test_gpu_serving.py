@@ -133,3 +133,23 @@ def test_reload_refused_while_serving(torch_cuda, wl1):
         assert (ids >= 0).all()
     finally:
         c.close()
+
+
+def test_destroy_refused_while_serving(torch_cuda, wl1):
+    """uhnsw_destroy leaves a context alone while a server runs on it;
+    Context.close stops the servers first."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    c = uhnsw.Context(0)
+    c.load_graphs(wl.base, g1, g2)
+    srv = uhnsw.Server(c, k_max=10, ef_max=64)
+    uhnsw.uhnsw_destroy(c.h)  # refused: the server's thread uses the context
+    assert b"refused" in uhnsw.uhnsw_last_error(c.h)
+    assert srv.submit(wl.queries[0], float(wl.p[0]), 10, 64, 3) == uhnsw.UHNSW_OK
+    got = []
+    while not got:
+        got = srv.poll()
+    assert got[0].tag == 3 and got[0].status == 0
+    c.close()  # stops the server, then frees the context
+    assert srv.h is None and c.h is None
