@@ -107,3 +107,17 @@ def test_index_file_layouts(tmp_path):
             nodes = np.frombuffer(b[at:at + 4 * nl], np.int32); at += 4 * nl
             np.testing.assert_array_equal(nodes, L.nodes)
     assert at == len(b)
+
+
+def test_extended_workloads_share_vectors():
+    """Workloads 6 and 7 (the extended variant's inputs) reuse workloads 1
+    and 2's vectors, queries and graph seed; only p changes, to (0.2, 1]
+    (6: uniform) and the 0.1 grid 0.2 .. 1.0 (7)."""
+    a, b = synth.make_workload(1), synth.make_workload(6)
+    assert np.array_equal(a.base, b.base) and np.array_equal(a.queries, b.queries)
+    assert a.graph_seed == b.graph_seed
+    assert (b.p > 0.2).all() and (b.p <= 1.0).all()
+    c = synth.make_workload(7, n=2000)
+    d = synth.make_workload(2, n=2000)
+    assert np.array_equal(c.base, d.base) and np.array_equal(c.queries, d.queries)
+    np.testing.assert_array_equal(np.unique(c.p), synth.P_GRID_EXT)
