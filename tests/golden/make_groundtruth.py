@@ -16,6 +16,12 @@ definition of the U-HNSW paper, Sec. 4.1.2) on the seeded inputs from
 
     python tests/golden/make_groundtruth.py [--workload 2|3|4|5|7] [--threads N]
 
+With ``--ideal`` it prints (no file) the idealized recall behind the
+graph-choice cutoff (Sec. 3.2, Fig. 2): for the sweep's 200 queries, the
+share of the exact L_p top-K found among the exact top-t under the base
+metric L1 or L2, for each p of SWEEP_P and t in IDEAL_T (needs the sweep
+file).
+
 With ``--sweep`` it writes tests/golden/gt_sweep_<workload>.npz instead: the
 top-50 of every 50th query of workload 2 (200 queries) under each p of
 SWEEP_P, the paper's 0.1 grid over [0.5, 2] plus its ablation value 0.51
@@ -41,6 +47,39 @@ SIZE = {5: 1_000_000}  # workload -> reduced n
 K = 10
 SWEEP_P = np.array([0.5, 0.51] + [round(0.6 + 0.1 * i, 1) for i in range(15)], np.float32)
 SWEEP_K = 50
+IDEAL_T = (10, 30, 60, 100, 200, 300)
+
+
+def ideal(a):
+    wl = synth.make_workload(2)
+    gt = dict(np.load(os.path.join(HERE, f"gt_sweep_{wl.name}.npz")))
+    if bytes(gt["digest"]).decode() != wl.digest():
+        raise SystemExit("sweep ground truth does not match the generated workload")
+    qidx = gt["qidx"]
+    T = max(IDEAL_T)
+    base_top = {}
+    for metric in (1.0, 2.0):  # exact top-T under the base metric (L_1, L_2)
+        ids = np.empty((len(qidx), T), np.int32)
+        for s in range(0, len(qidx), 50):
+            sel = qidx[s:s + 50]
+            ids[s:s + 50], _ = oracle.bruteforce(wl.base, wl.queries[sel], np.full(len(sel), metric, np.float32), T,
+                                                 a.threads)
+        base_top[metric] = ids
+    out = {"workload": wl.name, "queries": len(qidx), "t": list(IDEAL_T), "rows": []}
+    for j, pv in enumerate(gt["p"]):
+        for K in (10, 50):
+            row = {"p": round(float(pv), 2), "K": K}
+            for metric, name in ((1.0, "L1"), (2.0, "L2")):
+                rec = []
+                for t in IDEAL_T:
+                    hit = [len(set(gt["ids"][j, i, :K].tolist()) & set(base_top[metric][i, :t].tolist())) / K
+                           for i in range(len(qidx))]
+                    rec.append(round(float(np.mean(hit)), 4))
+                row[name] = rec
+            out["rows"].append(row)
+    import json
+
+    print(json.dumps(out))
 
 
 def sweep(a):
@@ -66,9 +105,12 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--workload", type=int, default=2, choices=sorted(SAMPLE))
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--ideal", action="store_true")
     a = ap.parse_args()
     if a.sweep:
         return sweep(a)
+    if a.ideal:
+        return ideal(a)
     wl = synth.make_workload(a.workload, n=SIZE.get(a.workload))
     first, stride = SAMPLE[a.workload]
     qidx = np.arange(first, wl.nq, stride, dtype=np.int32)
