@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source, the host
 # code that plans its launch (cache size, block shape) and ef.
-TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "bd7e3db9449d5ff1", "ef": 256,
-           "bytes_per_launch": 25.010e9}
+TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "f6175f28390487f3", "ef": 256,
+           "bytes_per_launch": 25.011e9}
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
 HOST_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_host.cpp")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
