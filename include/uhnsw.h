@@ -165,13 +165,29 @@ void uhnsw_destroy(uhnsw_ctx *ctx);
  * The string is owned by the library and valid until the next call on ctx. */
 const char *uhnsw_last_error(const uhnsw_ctx *ctx);
 
+/* Recover a context that a device error (EDEVICE, or ENOMEM from a device
+ * allocation) marked failed; a failed context answers every search with
+ * ESTATE until this call or a successful uhnsw_load_graphs. Not an
+ * operation of the method: it lets a caller that keeps one context for its
+ * lifetime (a service answering query tuples as in the problem statement,
+ * Sec. 1.1) go on after a failure. Waits for the device, then drops the
+ * captured hipGraphs and all per-stream and staging scratch (reallocated on
+ * next use); the loaded index stays. A context that is not failed is reset
+ * the same way.
+ * Errors: EINVAL (NULL), ESTATE (a server is running on the context),
+ * EDEVICE (the device still reports an error: the context stays failed and
+ * should be destroyed). */
+int uhnsw_reset(uhnsw_ctx *ctx);
+
 /* Validate the index and copy it to the device, replacing any loaded index.
  * Layer 0 becomes fixed-degree rows of 2M ids (-1 padded); upper layers get
  * M-wide rows addressed through a per-node offset; base vectors get a padded
  * row pitch (zeros) and, for BF16/F16 storage, a converted walk copy.
  * Errors: EINVAL (any structural violation: id out of range, degree above
- * 2M / M, neighbour not on the layer, entry point not on the top layer,
- * d > UHNSW_DMAX, M0 > 64, a non-finite base value, an unknown variant),
+ * 2M / M, neighbour not on the layer, a row listing one neighbour twice or
+ * the node itself (a neighbour list is a set of other nodes, Sec. 2.2),
+ * entry point not on the top layer, d > UHNSW_DMAX, M0 > 64, a non-finite
+ * base value, an unknown variant),
  * ESTATE (a server is running on the context), ENOMEM, EDEVICE. */
 int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
 

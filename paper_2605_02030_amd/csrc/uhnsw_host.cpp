@@ -46,11 +46,16 @@ struct DevBuf {
 // streams one context serves at once (each holds its own search scratch)
 constexpr int kMaxStreams = 64;
 
+// What a captured launch sequence depends on besides the kernels: the
+// caller's pointers and sizes, the knobs, and `gen`, the context's scratch
+// generation (bumped whenever a scratch buffer the kernels may address is
+// reallocated), so a graph that baked in freed scratch is never replayed.
 struct GraphKey {
     const void *ptrs[16];
     int64_t nq;
     int32_t ints[4];
     uhnsw_params prm;
+    uint64_t gen;
 };
 
 struct GraphDev {
@@ -77,8 +82,7 @@ struct uhnsw_ctx {
     int64_t pitch = 0;
     DevBuf f32_base, walk_base;
     GraphDev g[2];
-    DevBuf mtab;
-    double mtab_tau = -1.0;
+    uint64_t scratch_gen = 0;  // bumped on every scratch reallocation (GraphKey)
     // Per-launch-stream scratch: searches on different streams may run
     // concurrently, so everything a search writes besides the caller's
     // outputs (candidate lists, counts, default stats, the work counter,
@@ -198,21 +202,34 @@ int check_graph(std::string *c, const uhnsw_graph &g, int64_t n, int which) {
             return fail(c, UHNSW_EINVAL, "%s: layer %d lists %lld nodes, levels say %lld", nm, l, (long long)rows,
                         (long long)on_layer);
         if (rp[0] != 0) return fail(c, UHNSW_EINVAL, "%s: layer %d row_ptr[0] != 0", nm, l);
+        for (int64_t r = 0; l > 0 && r < rows; ++r) {
+            const int32_t v = g.nodes[l][r];
+            if (v < 0 || v >= n || g.level[v] < l || (r > 0 && g.nodes[l][r - 1] >= v))
+                return fail(c, UHNSW_EINVAL, "%s: layer %d nodes not ascending ids on the layer", nm, l);
+        }
         for (int64_t r = 0; r < rows; ++r) {
-            if (l > 0) {
-                const int32_t v = g.nodes[l][r];
-                if (v < 0 || v >= n || g.level[v] < l || (r > 0 && g.nodes[l][r - 1] >= v))
-                    return fail(c, UHNSW_EINVAL, "%s: layer %d nodes not ascending ids on the layer", nm, l);
-            }
             const int64_t deg = rp[r + 1] - rp[r];
             if (deg < 0 || deg > deg_max)
                 return fail(c, UHNSW_EINVAL, "%s: layer %d row %lld degree %lld outside [0, %d]", nm, l,
                             (long long)r, (long long)deg, deg_max);
+            const int32_t self = l == 0 ? (int32_t)r : g.nodes[l][r];
+            int32_t row[kWave];
             for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
                 const int32_t u = col[e];
                 if (u < 0 || u >= n || g.level[u] < l)
                     return fail(c, UHNSW_EINVAL, "%s: layer %d edge to %d not on the layer", nm, l, u);
+                if (u == self)
+                    return fail(c, UHNSW_EINVAL, "%s: layer %d node %d lists itself as a neighbour", nm, l, u);
+                row[e - rp[r]] = u;
             }
+            // An HNSW neighbour list is a set (Sec. 2.2): the walk marks a
+            // neighbour visited only after all of a row's ids were tested,
+            // so an id listed twice would enter the candidate list twice.
+            std::sort(row, row + deg);
+            for (int64_t e = 1; e < deg; ++e)
+                if (row[e] == row[e - 1])
+                    return fail(c, UHNSW_EINVAL, "%s: layer %d node %d lists neighbour %d twice", nm, l, self,
+                                row[e]);
         }
     }
     return UHNSW_OK;
@@ -312,15 +329,25 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     return UHNSW_OK;
 }
 
-int ensure_mtab(uhnsw_ctx *c, double tau) {
-    if (c->mtab.p && c->mtab_tau == tau) return UHNSW_OK;
-    int32_t tab[UHNSW_KMAX + 1];
+// Algorithm 1's stop test |R_new n R| / K >= tau as the integer test
+// |R_new n R| >= m, m = ceil(tau K) (the 1e-9 guard keeps 0.92 * 100 at 92);
+// m above K never fires, so it is capped at K + 1.
+void fill_mtab(double tau, uint16_t *tab) {
     tab[0] = 0;
-    for (int K = 1; K <= UHNSW_KMAX; ++K) tab[K] = (int32_t)std::ceil(tau * (double)K - 1e-9);
-    HIP_OR_FAIL(c, c->mtab.ensure(sizeof tab));
-    HIP_OR_FAIL(c, hipMemcpy(c->mtab.p, tab, sizeof tab, hipMemcpyHostToDevice));
-    c->mtab_tau = tau;
-    return UHNSW_OK;
+    for (int K = 1; K <= UHNSW_KMAX; ++K) {
+        const double m = std::ceil(tau * (double)K - 1e-9);
+        tab[K] = (uint16_t)(m > K ? K + 1 : (m < 0 ? 0 : m));
+    }
+}
+
+// Scratch that the kernels address: a reallocation moves it, so every
+// captured graph that may hold the old address is invalidated.
+hipError_t ensure_scratch(uhnsw_ctx *c, DevBuf &b, size_t want) {
+    void *old = b.p;
+    const size_t old_bytes = b.bytes;
+    hipError_t e = b.ensure(want);
+    if (b.p != old || b.bytes != old_bytes) ++c->scratch_gen;
+    return e;
 }
 
 int check_params(uhnsw_ctx *c, const uhnsw_params &prm) {
@@ -550,7 +577,7 @@ void uhnsw_destroy(uhnsw_ctx *c) {
         if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
     }
     c->sets.clear();
-    DevBuf *bufs[] = {&c->f32_base, &c->walk_base, &c->mtab, &c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids,
+    DevBuf *bufs[] = {&c->f32_base, &c->walk_base, &c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids,
                       &c->s_dists, &c->s_stats};
     for (DevBuf *b : bufs) b->reset();
     for (auto &g : c->g) {
@@ -568,6 +595,38 @@ void uhnsw_destroy(uhnsw_ctx *c) {
 }
 
 const char *uhnsw_last_error(const uhnsw_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int uhnsw_reset(uhnsw_ctx *c) {
+    if (!c) return UHNSW_EINVAL;
+    if (c->servers.load() > 0) return fail(c, UHNSW_ESTATE, "uhnsw_reset refused: a server is running");
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipGetLastError();  // clear a non-sticky error left by the failure
+    if (e != hipSuccess) {
+        c->failed = true;
+        return fail(c, UHNSW_EDEVICE, "uhnsw_reset: the device still reports %s; destroy the context",
+                    hipGetErrorString(e));
+    }
+    // Everything a failed call may have left half made: captured graphs and
+    // the per-stream and staging scratch (reallocated on next use).
+    for (auto &S : c->sets) {
+        if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+        S->gexec = nullptr;
+        S->gkey = GraphKey{};
+        DevBuf *sb[] = {&S->cand_ids, &S->cand_keys, &S->ncand, &S->stats, &S->counter, &S->o_entry,
+                        &S->o_ekey, &S->o_dnb, &S->o_dist, &S->o_misc, &S->o_order};
+        for (DevBuf *b : sb) b->reset();
+    }
+    if (c->hgexec) (void)hipGraphExecDestroy(c->hgexec);
+    c->hgexec = nullptr;
+    c->hgkey = GraphKey{};
+    DevBuf *bufs[] = {&c->s_q, &c->s_p, &c->s_k, &c->s_ef, &c->s_ids, &c->s_dists, &c->s_stats};
+    for (DevBuf *b : bufs) b->reset();
+    ++c->scratch_gen;
+    c->failed = false;
+    c->err.clear();
+    return UHNSW_OK;
+}
 
 int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     if (!c) return UHNSW_EINVAL;
@@ -712,7 +771,6 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     if ((r = make_plan(c, k_max, ef_max, prm, &pl))) return r;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_OR_FAIL(c, hipSetDevice(c->device));
-    if ((r = ensure_mtab(c, prm.tau))) return r;
 
     SearchArgs a{};
     a.walk_base = c->storage == UHNSW_STORE_F32 ? c->f32_base.p : c->walk_base.p;
@@ -746,7 +804,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     a.kappa_param = prm.kappa;
     a.beam = prm.beam_width;
     a.early_abort = prm.early_abort;
-    a.mtab = c->mtab.as<int32_t>();
+    fill_mtab(prm.tau, a.mtab);
     a.ef_cap = pl.ef_cap;
     a.vis_bits = pl.vis_bits;
     a.vis_kbits = pl.vis_kbits;
@@ -760,7 +818,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     if (stats) {
         a.stats = stats;
     } else {
-        HIP_OR_FAIL(c, S->stats.ensure((size_t)nq * sizeof(uhnsw_stats)));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->stats, (size_t)nq * sizeof(uhnsw_stats)));
         a.stats = S->stats.as<uhnsw_stats>();
     }
     if (prm.fused) {
@@ -771,10 +829,10 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     } else {
         const int32_t cs = cand_ids ? c_stride : ef_max;
         if (!cand_ids) {
-            HIP_OR_FAIL(c, S->cand_ids.ensure((size_t)nq * cs * 4));
-            HIP_OR_FAIL(c, S->cand_keys.ensure((size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_ids, (size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_keys, (size_t)nq * cs * 4));
         }
-        HIP_OR_FAIL(c, S->ncand.ensure((size_t)nq * 4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->ncand, (size_t)nq * 4));
         a.cand_ids = cand_ids ? cand_ids : S->cand_ids.as<int32_t>();
         a.cand_keys = cand_ids ? cand_keys : S->cand_keys.as<float>();
         a.c_stride = cs;
@@ -782,16 +840,16 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     }
     const bool ordered = prm.persistent >= 2;
     const bool counted = prm.persistent == 1 || prm.persistent == 2;  // 3: ordered static grid
-    if (counted) HIP_OR_FAIL(c, S->counter.ensure(4));
+    if (counted) HIP_OR_FAIL(c, ensure_scratch(c, S->counter, 4));
     OrderArgs oa{};
     if (ordered) {
         const size_t q4 = (size_t)nq * 4;
-        HIP_OR_FAIL(c, S->o_entry.ensure(q4));
-        HIP_OR_FAIL(c, S->o_ekey.ensure(q4));
-        HIP_OR_FAIL(c, S->o_dnb.ensure(q4));
-        HIP_OR_FAIL(c, S->o_dist.ensure(q4));
-        HIP_OR_FAIL(c, S->o_order.ensure(q4));
-        HIP_OR_FAIL(c, S->o_misc.ensure((6 + 2 * kOrderBuckets) * 4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_entry, q4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_ekey, q4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_dnb, q4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_dist, q4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_order, q4));
+        HIP_OR_FAIL(c, ensure_scratch(c, S->o_misc, (6 + 2 * kOrderBuckets) * 4));
         oa.entry = S->o_entry.as<int32_t>();
         oa.ekey = S->o_ekey.as<float>();
         oa.dnb = S->o_dnb.as<int32_t>();
@@ -882,6 +940,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     key.prm = prm;
     key.prm.timing = 0;
     key.prm.graph = 0;
+    key.gen = c->scratch_gen;
     if (!S->gexec || std::memcmp(&key, &S->gkey, sizeof key) != 0) {
         if (S->gexec) {
             (void)hipGraphExecDestroy(S->gexec);
@@ -1168,13 +1227,13 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     if (k_stride < k_max) return fail(c, UHNSW_EINVAL, "k_stride=%d < max k=%d", k_stride, k_max);
     HIP_OR_FAIL(c, hipSetDevice(c->device));
     const size_t nqs = (size_t)nq;
-    HIP_OR_FAIL(c, c->s_q.ensure(nqs * c->d * 4));
-    HIP_OR_FAIL(c, c->s_p.ensure(nqs * 4));
-    HIP_OR_FAIL(c, c->s_k.ensure(nqs * 4));
-    HIP_OR_FAIL(c, c->s_ef.ensure(nqs * 4));
-    HIP_OR_FAIL(c, c->s_ids.ensure(nqs * k_stride * 8));
-    HIP_OR_FAIL(c, c->s_dists.ensure(nqs * k_stride * 4));
-    HIP_OR_FAIL(c, c->s_stats.ensure(nqs * sizeof(uhnsw_stats)));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_q, nqs * c->d * 4));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_p, nqs * 4));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_k, nqs * 4));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_ef, nqs * 4));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_ids, nqs * k_stride * 8));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_dists, nqs * k_stride * 4));
+    HIP_OR_FAIL(c, ensure_scratch(c, c->s_stats, nqs * sizeof(uhnsw_stats)));
     hipStream_t s = c->stream;
     uhnsw_ctx::StreamSet *S = nullptr;
     if (int r = stream_set(c, s, &S)) return r;
@@ -1238,6 +1297,7 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     key.ints[1] = ef_max;
     key.ints[2] = k_stride;
     key.prm = pr;
+    key.gen = c->scratch_gen;
     if (c->hgexec && !grown && std::memcmp(&key, &c->hgkey, sizeof key) == 0) {
         HIP_OR_FAIL(c, hipGraphLaunch(c->hgexec, s));
         HIP_OR_FAIL(c, hipStreamSynchronize(s));
@@ -1260,6 +1320,7 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
         hipError_t e = hipGraphInstantiate(&c->hgexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return dev_fail(c, e, "hipGraphInstantiate (host path)");
+        key.gen = c->scratch_gen;  // the scratch the captured kernels address
         c->hgkey = key;
         ++c->graph_captures;
     }

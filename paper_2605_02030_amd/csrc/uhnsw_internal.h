@@ -56,7 +56,10 @@ struct SearchArgs {
     // Algorithm 1 parameters
     float cutoff;
     int32_t t_param, kappa_param, beam, early_abort;
-    const int32_t *mtab;    // [UHNSW_KMAX + 1]: ceil(tau * K)
+    // m = ceil(tau * K) for K = 0 .. UHNSW_KMAX, capped at K + 1 (a count of
+    // at most K never reaches it): passed by value, so every launch and every
+    // captured graph carries its own tau's table
+    uint16_t mtab[UHNSW_KMAX + 1];
     // LDS plan (per wave)
     int32_t ef_cap, vis_bits, vis_kbits, kv_cap, lds_wave_bytes, waves_per_block;
     // candidate lists (walk -> verify)

@@ -27,7 +27,7 @@ EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
            "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files", "uhnsw_check_index",
-           "uhnsw_check_index_files")
+           "uhnsw_check_index_files", "uhnsw_reset")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -89,6 +89,7 @@ uhnsw_create = _sig("uhnsw_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(
 uhnsw_destroy = _sig("uhnsw_destroy", None, [_P])
 uhnsw_last_error = _sig("uhnsw_last_error", ctypes.c_char_p, [_P])
 uhnsw_load_graphs = _sig("uhnsw_load_graphs", ctypes.c_int, [_P, _P])
+uhnsw_reset = _sig("uhnsw_reset", ctypes.c_int, [_P])
 uhnsw_search = _sig("uhnsw_search", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _I32, _P, _P, _P])
 uhnsw_search_device = _sig("uhnsw_search_device", ctypes.c_int,
                            [_P, _P, _I64, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _I32, _P])
@@ -224,6 +225,10 @@ class Context:
         self._check(uhnsw_load_graphs(self.h, ctypes.byref(idx)))
         self.n, self.d = int(idx.n), int(idx.d)
         del keep
+
+    def reset(self) -> None:
+        """uhnsw_reset: clear a failed state (the loaded index stays)."""
+        self._check(uhnsw_reset(self.h))
 
     def layout(self):
         g, v = _I32(), _I32()

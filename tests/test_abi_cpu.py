@@ -89,5 +89,6 @@ def test_null_arguments_rejected_without_device(lib):
     # these return before touching the HIP runtime
     assert lib.uhnsw_create(0, None) == lib.UHNSW_EINVAL
     assert lib.uhnsw_load_graphs(None, None) == lib.UHNSW_EINVAL
+    assert lib.uhnsw_reset(None) == lib.UHNSW_EINVAL
     assert lib.uhnsw_search(None, None, 0, None, None, None, None, 0, None, None, None) == lib.UHNSW_EINVAL
     lib.uhnsw_destroy(None)

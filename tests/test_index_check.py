@@ -79,6 +79,16 @@ def _damage(g, what):
             pytest.skip("layer 1 too small")
         L1.nodes = L1.nodes.copy()
         L1.nodes[[0, 1]] = L1.nodes[[1, 0]]
+    elif what in ("dup_layer0", "dup_layer1"):  # one row lists a neighbour twice
+        L = L0 if what == "dup_layer0" else L1
+        r = int(np.flatnonzero(np.diff(L.row_ptr) >= 2)[0])
+        L.col = L.col.copy()
+        L.col[L.row_ptr[r] + 1] = L.col[L.row_ptr[r]]
+    elif what in ("self_loop_layer0", "self_loop_layer1"):  # a node lists itself
+        L = L0 if what == "self_loop_layer0" else L1
+        r = int(np.flatnonzero(np.diff(L.row_ptr) >= 1)[0])
+        L.col = L.col.copy()
+        L.col[L.row_ptr[r]] = r if L.nodes is None else int(L.nodes[r])
     elif what == "nodes_count_wrong":  # drop the last node of layer 1
         L1.nodes = L1.nodes[:-1].copy()
         L1.row_ptr = L1.row_ptr[:-1].copy()
@@ -95,7 +105,8 @@ DAMAGES = {"M_zero": "M=0 outside", "M_wide": "M=33 outside", "edge_out_of_range
            "row_ptr_decreasing": "row 1 degree -1", "entry_not_on_top": "not on the top layer",
            "entry_out_of_range": "entry point out of range", "max_level_wrong": "not on the top layer",
            "level_negative": "level[5] out of range", "nodes_unsorted": "not ascending",
-           "nodes_count_wrong": "levels say"}
+           "nodes_count_wrong": "levels say", "dup_layer0": "twice", "dup_layer1": "twice",
+           "self_loop_layer0": "lists itself", "self_loop_layer1": "lists itself"}
 
 
 @pytest.mark.parametrize("which", [0, 1])
