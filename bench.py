@@ -26,6 +26,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -46,7 +47,10 @@ HBM_PEAK_GBS = 8000.0
 # code that plans its launch (cache size, block shape) and ef.
 TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "f6175f28390487f3", "ef": 256,
            "bytes_per_launch": 25.011e9}
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_kernels.hip")
+# the sources the kernels are compiled from (hashed to tie the counter traffic
+# to the code it was measured on)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_02030_amd", "csrc", f)
+               for f in ("uhnsw_device.h", "uhnsw_walk_part.hip", "uhnsw_kernels.hip", "uhnsw_internal.h")]
 HOST_SRC = os.path.join(ROOT, "paper_2605_02030_amd", "csrc", "uhnsw_host.cpp")
 GT_PATH = os.path.join(ROOT, "tests", "golden", "gt_mixture-1M-d128.npz")
 EF_GRID = (32, 64, 128, 256)
@@ -109,10 +113,11 @@ class Form:
             log(f"{self.name} ef={ef}: autotuned beam={t.beam_width} slots={t.visited_slots} "
                 f"wpb={t.waves_per_block} persistent={t.persistent}")
 
-    def step(self, timing=False):
+    def step(self, timing=False, graph=True):
         if self.persistent:  # batching form: fused persistent launch, autotuned, replayed as a hipGraph
             prm = self.uhnsw.uhnsw_params.from_buffer_copy(self.tuned[self.ef_val])
             prm.timing = int(timing)
+            prm.graph = int(graph)
         else:
             prm = self.uhnsw.default_params(timing=int(timing))
         j = self.n_steps % self.pipeline
@@ -173,39 +178,54 @@ def calibrate(form, gt, log_prefix, grid=EF_GRID):
 
 
 def timed(form, steps, warmup, wl, rate_khz):
+    """Time `steps` steps after `warmup`. Kernel times come from HIP events on
+    the launch stream: the pre-pass, the walk (or fused) kernel and the
+    verification kernel separately (the batched forms: from one uncaptured
+    launch with the same knobs after the timed region)."""
     torch = form.torch
     for _ in range(warmup):
         form.step()
     torch.cuda.synchronize()
-    walk_ms, verify_ms = [], []
+    split = []
     t0 = time.perf_counter()
     for _ in range(steps):
         if form.pipeline > 1:  # steps overlap: no per-step wait
             form.step()
             continue
         form.step(timing=True)
-        w, v = form.ctx.last_timing()  # waits for this step's events
-        walk_ms.append(w)
-        verify_ms.append(v)
+        split.append(form.ctx.last_timing_split())  # waits for this step's events
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    if form.pipeline > 1:  # one launch's own duration, measured alone after the timed region
-        form.step(timing=True)
-        w, v = form.ctx.last_timing()
-        walk_ms.append(w)
-        verify_ms.append(v)
+    if form.pipeline > 1:  # one launch's own kernels, measured alone after the timed region
+        for _ in range(3):
+            form.step(timing=True, graph=False)
+            split.append(form.ctx.last_timing_split())
+    pre, walk, ver = (float(np.mean([x[i] for x in split])) for i in range(3))
     st = form.stats_np()
     t0c = st["t_begin"].astype(np.int64)
     t1c = st["t_end"].astype(np.int64)
     start = t0c.min()
     lat_ms = ((t1c - start) % (1 << 32)) / rate_khz  # ticks -> ms
-    M0 = 32
-    walk_bytes = float((st["n_b"].astype(np.float64) * wl.d * form.row_bytes_per_elem).sum()
-                       + (st["n_exp"].astype(np.float64) * M0 * 4).sum())
-    return dict(total_s=total, walk_ms=float(np.mean(walk_ms)), verify_ms=float(np.mean(verify_ms)),
-                p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)),
-                walk_bytes=walk_bytes, n_b=float(st["n_b"].mean()), n_exp=float(st["n_exp"].mean()),
-                n_p=float(st["n_p"].mean()), flags=int((st["flags"] != 0).sum()))
+    return dict(total_s=total, prepass_ms=pre, walk_ms=walk, verify_ms=ver,
+                p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)), stats=st,
+                n_b=float(st["n_b"].mean()), n_exp=float(st["n_exp"].mean()), n_p=float(st["n_p"].mean()),
+                flags=int((st["flags"] != 0).sum()))
+
+
+def method_bytes(wl, elem, gpu_st, counts, fused):
+    """Bytes the method itself reads in one launch of the walk (or fused)
+    kernel: the layer-0 rows N_b - N_up of d x elem bytes and the N_exp
+    adjacency rows of 2M = 32 ids (128 B) per query, with N_b and N_exp from
+    the oracle's walk over an exact visited set (the descent's N_up rows are
+    the pre-pass kernel's, and identical on both sides); the fused kernel
+    also reads the N_p FP32 rows it verifies. Returns (walk-kernel bytes,
+    pre-pass bytes)."""
+    up = gpu_st["n_up"].astype(np.float64).sum()
+    l0 = counts["n_b"].astype(np.float64).sum() - up
+    walk = l0 * wl.d * elem + counts["n_exp"].astype(np.float64).sum() * 32 * 4
+    if fused:
+        walk += gpu_st["n_p"].astype(np.float64).sum() * wl.d * 4
+    return float(walk), float(up * wl.d * elem)
 
 
 def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000, 400_000), seconds=0.5,
@@ -248,24 +268,72 @@ def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 20
                 k=sorted(set(int(x) for x in np.unique(kq))), rates=out)
 
 
-def cpu_baseline(wl, g1, g2, ef, budget_s=15.0, variant=0):
-    """The oracle (plain C, OpenMP over queries) on a bounded query sample."""
+def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # lscpu missing: fall back to /proc
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, g1, g2, ef, variant=0, combos=(), runs=5):
+    """The oracle (plain C, OpenMP over queries) timed on the host cores, and
+    the method's own work per query from the same runs.
+
+    Timed: all queries of the workload at `ef` with the paper's beam width 1
+    and FP32 rows, the median of `runs` runs after one warm-up, on
+    OMP_NUM_THREADS threads (the host's CPU share; every core when unset),
+    plus one single-thread run over the first 500 queries.
+
+    Method counts: for each (ef, beam width, storage) a GPU form ran with,
+    the oracle's N_b and N_exp per query, from its walk over an exact visited
+    set: the rows the method reads, without the re-reads the GPU's bounded
+    visited cache causes. These are the algorithmic bytes of the roofline."""
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(os.cpu_count() or 1, 16)
-    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
-    prm = oracle.Params(variant=variant, cutoff=0.6 if variant else 1.4)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or 0) or len(os.sched_getaffinity(0))
+    G1, G2 = oracle.Graph(g1), oracle.Graph(g2)
     efa = np.full(wl.nq, ef, np.int32)
-    n = 64
-    while True:
+
+    def prm(w=1):
+        return oracle.Params(variant=variant, cutoff=0.6 if variant else 1.4, w=w)
+
+    D32 = oracle.Data(wl.base)
+    oracle.query_batch(G1, G2, D32, wl.queries, wl.p, wl.k, efa, prm(), threads=threads)  # warm-up
+    times, out = [], None
+    for _ in range(runs):
         t0 = time.perf_counter()
-        oracle.query_batch(G1, G2, D, wl.queries[:n], wl.p[:n], wl.k[:n], efa[:n], prm, threads=threads)
-        dt = time.perf_counter() - t0
-        if dt > budget_s / 4 or n >= wl.nq:
-            break
-        n = min(wl.nq, int(n * max(2.0, budget_s / 3 / max(dt, 1e-3))))
-    return dict(value=round(n / dt, 1), unit="queries/s", cores=threads, kind="oracle",
-                sample=f"first {n} of {wl.nq} queries, ef={ef}, same graphs/params, {dt:.1f}s wall")
+        out = oracle.query_batch(G1, G2, D32, wl.queries, wl.p, wl.k, efa, prm(), threads=threads)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    n1 = min(500, wl.nq)
+    t0 = time.perf_counter()
+    oracle.query_batch(G1, G2, D32, wl.queries[:n1], wl.p[:n1], wl.k[:n1], efa[:n1], prm(), threads=1)
+    dt1 = time.perf_counter() - t0
+    counts = {(ef, 1, 0): out["stats"]}
+    storages = {0: D32}
+    for e, w, storage in sorted(set(combos)):
+        if (e, w, storage) in counts:
+            continue
+        if storage not in storages:
+            storages[storage] = oracle.Data(wl.base, storage=storage)
+        counts[(e, w, storage)] = oracle.query_batch(G1, G2, storages[storage], wl.queries, wl.p, wl.k,
+                                                     np.full(wl.nq, e, np.int32), prm(w), threads=threads)["stats"]
+    base = dict(value=round(wl.nq / dt, 1), unit="queries/s", cores=threads, kind="oracle",
+                sample=f"all {wl.nq} queries at ef={ef}, beam 1, FP32 rows, same graphs and parameters; "
+                       f"median of {runs} runs ({', '.join(f'{t:.2f}' for t in times)} s)",
+                single_core_qps=round(n1 / dt1, 1), single_core_sample=f"first {n1} queries, 1 thread",
+                nproc=os.cpu_count(), affinity_cpus=len(os.sched_getaffinity(0)), cpu_model=_cpu_model())
+    return base, counts
 
 
 def gt_for(wl):
@@ -584,12 +652,11 @@ def main():
     forms = {}
     specs = {"fp32": (uhnsw.STORE_F32, 0, 4), "bf16-batched": (uhnsw.STORE_BF16, 1, 2),
              "fp32-batched": (uhnsw.STORE_F32, 1, 4), "fp16-batched": (uhnsw.STORE_F16, 1, 2)}
-    chosen_fp32 = None
+    runs = {}  # form -> (ef, beam, storage, elem, fused, timing dict)
     probes = None
     for name in [f.strip() for f in a.forms.split(",") if f.strip()]:
         storage, persistent, elem = specs[name]
         f = Form(torch, uhnsw, wl, g1, g2, storage, persistent, name, variant)
-        f.row_bytes_per_elem = elem
         num_cus, rate_khz = f.ctx.device_info()
         if name == "fp32":  # ceiling probes on the resident FP32 rows (512 B per row)
             probes = dict(gather_512B_gbs=round(f.ctx.probe_gather(512), 1),
@@ -604,37 +671,80 @@ def main():
         r = timed(f, a.steps, a.warmup, wl, rate_khz)
         rec = recall_at_k(f.ids.cpu().numpy(), gt["ids"], gt["qidx"])
         qps = wl.nq * a.steps / r["total_s"]
-        achieved = r["walk_bytes"] / (r["walk_ms"] * 1e-3) / 1e9
-        forms[name] = dict(ef=ef, recall_at_10=round(rec, 4), qps=round(qps, 1),
+        beam = f.tuned[ef].beam_width if persistent else 1
+        forms[name] = dict(ef=ef, beam=beam, recall_at_10=round(rec, 4), qps=round(qps, 1),
                            ms_per_step=round(r["total_s"] * 1e3 / a.steps, 4), p50_ms=round(r["p50_ms"], 4),
-                           p99_ms=round(r["p99_ms"], 4), walk_ms=round(r["walk_ms"], 4),
-                           verify_ms=round(r["verify_ms"], 4), walk_gbs=round(achieved, 1),
+                           p99_ms=round(r["p99_ms"], 4), prepass_ms=round(r["prepass_ms"], 4),
+                           walk_ms=round(r["walk_ms"], 4), verify_ms=round(r["verify_ms"], 4),
                            mean_n_b=round(r["n_b"], 1), mean_n_exp=round(r["n_exp"], 1),
                            mean_n_p=round(r["n_p"], 2), flagged=r["flags"], sweep=table)
-        if f.pipeline > 1:  # walk_ms / walk_gbs: one launch alone; step_gbs: per step with overlap
-            forms[name].update(streams=f.pipeline,
-                               step_gbs=round(r["walk_bytes"] / (r["total_s"] / a.steps) / 1e9, 1))
+        if persistent:
+            t = f.tuned[ef]
+            forms[name].update(streams=f.pipeline, slots=t.visited_slots, wpb=t.waves_per_block,
+                               schedule=t.persistent, waves_per_cu=t.waves_per_cu)
+        runs[name] = (ef, beam, storage, elem, bool(persistent), r)
         # the host-pointer entry point (PCIe copies in and out included); left
         # out of --copy-probe runs, whose 1 GiB copies must be the only large
         # copy dispatches the counter scaling reads, and of --no-host-api runs
         if name == "fp32" and not a.copy_probe and not a.no_host_api:
             forms[name]["host_api_qps"] = host_api_qps(f, wl, ef, uhnsw)
         log(name, json.dumps(forms[name]))
-        if name == "fp32":
-            chosen_fp32 = (ef, r, achieved)
         f.ctx.close()
         del f
         torch.cuda.empty_cache()
 
-    import hashlib
-
-    with open(KERNEL_SRC, "rb") as fh:
-        kernel_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
-    with open(HOST_SRC, "rb") as fh:
-        host_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
     main_name = "fp32" if "fp32" in forms else next(iter(forms))
     m = forms[main_name]
-    ef_main, r_main, ach_main = chosen_fp32 if chosen_fp32 else (m["ef"], None, m["walk_gbs"])
+    serving_out = None
+    if not a.no_serving:
+        serving_out = serving(torch, uhnsw, wl, g1, g2, gt, m["ef"], variant=variant)
+    baseline, counts = None, {}
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle) and the method's own row counts ...")
+        baseline, counts = cpu_baseline(wl, g1, g2, m["ef"], variant=variant,
+                                        combos=[(v[0], v[1], v[2]) for v in runs.values()])
+        log("cpu baseline", json.dumps(baseline))
+    # per form: the method's bytes over the walk kernel's own time; the GPU's
+    # rows over the method's rows (re-reads after the visited cache forgot a node)
+    for name, (ef, beam, storage, elem, fused, r) in runs.items():
+        c = counts.get((ef, beam, storage))
+        if c is None:
+            continue
+        wb, pb = method_bytes(wl, elem, r["stats"], c, fused)
+        fm = forms[name]
+        fm["method_bytes_per_launch"] = round(wb + pb)
+        fm["walk_gbs"] = round(wb / (r["walk_ms"] * 1e-3) / 1e9, 1)
+        fm["walk_frac_of_hbm_peak"] = round(wb / (r["walk_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        fm["gpu_rows_over_method_rows"] = round(float(r["stats"]["n_b"].astype(np.float64).sum()
+                                                      / c["n_b"].astype(np.float64).sum()), 4)
+        if fm.get("streams", 1) > 1:  # per step with two launches in flight
+            fm["step_gbs"] = round((wb + pb) / (r["total_s"] / a.steps) / 1e9, 1)
+            fm["step_frac_of_hbm_peak"] = round(fm["step_gbs"] / HBM_PEAK_GBS, 4)
+
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    kernel_hash = h.hexdigest()[:16]
+    with open(HOST_SRC, "rb") as fh:
+        host_hash = hashlib.sha256(fh.read()).hexdigest()[:16]
+    m = forms[main_name]
+    wb_main, _ = (method_bytes(wl, runs[main_name][3], runs[main_name][5]["stats"],
+                               counts[runs[main_name][:3]], runs[main_name][4])
+                  if runs[main_name][:3] in counts else (None, None))
+    walk_s = runs[main_name][5]["walk_ms"] * 1e-3
+    if wb_main is None:  # no oracle run: the kernel's own counters (re-reads included)
+        st = runs[main_name][5]["stats"]
+        wb_main = float((st["n_b"] - st["n_up"]).astype(np.float64).sum() * wl.d * runs[main_name][3]
+                        + st["n_exp"].astype(np.float64).sum() * 128)
+        bytes_from = "kernel counters (rows re-read after the visited cache forgot them included)"
+    else:
+        bytes_from = "oracle walk with an exact visited set (method's own rows)"
+    ach = wb_main / walk_s / 1e9
+    traffic_ok = (kernel_hash == TRAFFIC["kernel_sha256_prefix"] and host_hash == TRAFFIC["host_sha256_prefix"]
+                  and m["ef"] == TRAFFIC["ef"] and main_name == "fp32" and not ext)
     out = {
         "metric": "QPS at recall@10>=0.9 under mixed-p L_p (1 GPU)",
         "value": m["qps"],
@@ -655,20 +765,21 @@ def main():
         "recall_at_10": m["recall_at_10"],
         "p50_ms": m["p50_ms"],
         "p99_ms": m["p99_ms"],
-        "roofline": {"bound": "hbm", "achieved": round(ach_main, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach_main / HBM_PEAK_GBS, 4),
-                     "traffic": (TRAFFIC["bytes_per_launch"] if kernel_hash == TRAFFIC["kernel_sha256_prefix"]
-                                 and host_hash == TRAFFIC["host_sha256_prefix"] and m["ef"] == TRAFFIC["ef"]
-                                 and main_name == "fp32" and not ext else None),
-                     "kernel": "walk_kernel", "walk_ms": m["walk_ms"]},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": TRAFFIC["bytes_per_launch"] if traffic_ok else None,
+                     "kernel": "walk_kernel" if main_name == "fp32" else "search_kernel",
+                     "kernel_ms": round(walk_s * 1e3, 4), "algorithmic_bytes_per_launch": round(wb_main),
+                     "bytes_from": bytes_from,
+                     "traffic_over_algorithmic": round(TRAFFIC["bytes_per_launch"] / wb_main, 4)
+                     if traffic_ok else None},
         "probes": probes,
         "forms": forms,
     }
-    if not a.no_serving:
-        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, forms[main_name]["ef"], variant=variant)
-    if not a.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(wl, g1, g2, m["ef"], variant=variant)
+    if serving_out is not None:
+        out["serving"] = serving_out
+    if baseline is not None:
+        out["cpu_baseline"] = baseline
     print(json.dumps(out), flush=True)
 
 

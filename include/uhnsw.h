@@ -146,6 +146,8 @@ typedef struct {
                                  32 bits of a counter running at
                                  hipDeviceAttributeWallClockRate kHz           */
     uint32_t t_end;
+    int32_t n_up;             /* base distances of the upper-layer descent
+                                 (part of n_b; the rest are layer 0's)        */
 } uhnsw_stats;
 
 /* Fill *prm with the defaults above. */
@@ -299,8 +301,17 @@ int uhnsw_probe_transcendental(uhnsw_ctx *ctx, double *ops_per_s);
 int uhnsw_device_info(const uhnsw_ctx *ctx, int32_t *num_cus, int32_t *wall_clock_khz);
 
 /* Kernel times (ms) of the last search run with prm->timing = 1, measured
- * with HIP events on the stream the kernels ran on. */
+ * with HIP events on the stream the kernels ran on. walk_ms covers the
+ * descent pre-pass (schedules 2, 3) and the walk kernel (the fused kernel,
+ * verification included, with prm->fused); verify_ms the verification
+ * kernel (0 with prm->fused). */
 int uhnsw_last_timing(const uhnsw_ctx *ctx, float *walk_ms, float *verify_ms);
+
+/* The same search's times split three ways: prepass_ms the descent pre-pass
+ * and ordering kernels (0 without them), walk_ms the walk kernel alone (the
+ * fused kernel with prm->fused), verify_ms the verification kernel. A search
+ * replayed from a captured hipGraph has no split: ESTATE. */
+int uhnsw_last_timing_split(const uhnsw_ctx *ctx, float *prepass_ms, float *walk_ms, float *verify_ms);
 
 /* ------------------------------------------------------------ serving form
  * Continuous batching over the loaded index. Queries are admitted into

@@ -565,7 +565,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (lane == 0) {
             if (A.ncand) A.ncand[qi] = -1;
             st->graph = 0;
-            st->n_b = st->n_exp = st->n_p = st->batches = st->nc = 0;
+            st->n_b = st->n_exp = st->n_p = st->batches = st->nc = st->n_up = 0;
             st->flags = UHNSW_QBAD;
             st->entry0 = -1;
             st->t_begin = st->t_end = t_begin;
@@ -597,6 +597,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, root, L.sqt, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
     }
     const int32_t entry0 = cur;
+    const int n_up = n_b;  // the descent's base distances
 
     // ---- layer 0: best-first expansion of the sorted list W
     wave_sync();
@@ -719,6 +720,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (A.ncand) A.ncand[qi] = nc;
         st->graph = gsel + 1;
         st->n_b = n_b;
+        st->n_up = n_up;
         st->n_exp = n_exp;
         st->nc = nc;
         st->flags = flags;

@@ -91,8 +91,11 @@ struct uhnsw_ctx {
         hipStream_t stream = nullptr;
         DevBuf cand_ids, cand_keys, ncand, stats, counter;
         DevBuf o_entry, o_ekey, o_dnb, o_dist, o_misc, o_order;  // cost-ordered launch
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        // timing events: [0] start, [3] after the pre-pass, [1] after the
+        // walk (or fused) kernel, [2] after verification
+        hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
         bool timed = false;
+        bool split = false;  // ev[3] recorded (not a graph replay)
         hipGraphExec_t gexec = nullptr;
         GraphKey gkey{};
     };
@@ -731,6 +734,19 @@ int uhnsw_device_info(const uhnsw_ctx *c_, int32_t *num_cus, int32_t *wall_clock
     return UHNSW_OK;
 }
 
+int uhnsw_last_timing_split(const uhnsw_ctx *c_, float *prepass_ms, float *walk_ms, float *verify_ms) {
+    uhnsw_ctx *c = const_cast<uhnsw_ctx *>(c_);
+    if (!c || !prepass_ms || !walk_ms || !verify_ms) return UHNSW_EINVAL;
+    const auto *S = c->last_set;
+    if (!S || !S->timed) return fail(c, UHNSW_ESTATE, "no timed search yet");
+    if (!S->split) return fail(c, UHNSW_ESTATE, "the last timed search was a graph replay: no split");
+    HIP_OR_FAIL(c, hipEventSynchronize(S->ev[2]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(prepass_ms, S->ev[0], S->ev[3]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(walk_ms, S->ev[3], S->ev[1]));
+    HIP_OR_FAIL(c, hipEventElapsedTime(verify_ms, S->ev[1], S->ev[2]));
+    return UHNSW_OK;
+}
+
 int uhnsw_last_timing(const uhnsw_ctx *c_, float *walk_ms, float *verify_ms) {
     uhnsw_ctx *c = const_cast<uhnsw_ctx *>(c_);
     if (!c || !walk_ms || !verify_ms) return UHNSW_EINVAL;
@@ -898,6 +914,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
             b.ekey = oa.ekey;
             b.dnb = oa.dnb;
         }
+        if (timed && (e = hipEventRecord(S->ev[3], st)) != hipSuccess) return e;
         if (prm.fused) {
             b.lds_wave_bytes = pl.search_bytes;
             if ((e = launch_search(b, c->layout, counted ? pgrid : grid_all, st)) != hipSuccess) return e;
@@ -915,6 +932,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     };
 
     S->timed = prm.timing != 0;
+    S->split = S->timed && !prm.graph;
     c->last_set = S;
     if (!prm.graph) {
         HIP_OR_FAIL(c, enqueue(s, S->timed));

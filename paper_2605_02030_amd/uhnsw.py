@@ -27,7 +27,7 @@ EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
            "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files", "uhnsw_check_index",
-           "uhnsw_check_index_files", "uhnsw_reset")
+           "uhnsw_check_index_files", "uhnsw_reset", "uhnsw_last_timing_split")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -58,7 +58,7 @@ class uhnsw_params(ctypes.Structure):
 
 class uhnsw_stats(ctypes.Structure):
     _fields_ = [(f, _I32) for f in ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0")] + \
-               [("t_begin", ctypes.c_uint32), ("t_end", ctypes.c_uint32)]
+               [("t_begin", ctypes.c_uint32), ("t_end", ctypes.c_uint32), ("n_up", _I32)]
 
 
 class uhnsw_serve_config(ctypes.Structure):
@@ -72,8 +72,9 @@ class uhnsw_serve_result(ctypes.Structure):
                 ("ids", _I64 * UHNSW_KMAX), ("dists", ctypes.c_float * UHNSW_KMAX)]
 
 
-STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end")
-STATS_DTYPE = np.dtype([(f, np.int32) for f in STATS_FIELDS[:8]] + [(f, np.uint32) for f in STATS_FIELDS[8:]])
+STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end", "n_up")
+STATS_DTYPE = np.dtype([(f, np.int32) for f in STATS_FIELDS[:8]] + [(f, np.uint32) for f in STATS_FIELDS[8:10]]
+                       + [("n_up", np.int32)])
 STATS_WORDS = len(STATS_FIELDS)
 
 
@@ -106,6 +107,9 @@ uhnsw_serve_stop = _sig("uhnsw_serve_stop", ctypes.c_int, [_P])
 uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
                          [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)])
+uhnsw_last_timing_split = _sig("uhnsw_last_timing_split", ctypes.c_int,
+                               [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float)])
 uhnsw_probe_gather = _sig("uhnsw_probe_gather", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_double)])
 uhnsw_load_graph_files = _sig("uhnsw_load_graph_files", ctypes.c_int,
                               [_P, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, _I32])
@@ -329,6 +333,12 @@ class Context:
         self._check(uhnsw_last_timing(self.h, ctypes.byref(w), ctypes.byref(v)))
         return w.value, v.value
 
+    def last_timing_split(self):
+        """(pre-pass ms, walk kernel ms, verification ms) of the last timed search."""
+        a, w, v = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        self._check(uhnsw_last_timing_split(self.h, ctypes.byref(a), ctypes.byref(w), ctypes.byref(v)))
+        return a.value, w.value, v.value
+
 
 class Server:
     """Continuous-batching server on a Context (include/uhnsw.h, serving form)."""
@@ -368,8 +378,9 @@ class Server:
         return dict(zip(("slots", "free", "pending", "batches", "completed", "max_overlap", "max_batch",
                          "streams"), a.tolist()))
 
-    def drive(self, queries, p, k, ef, arrival_us):
-        """Submit on the given schedule, return (ids, dists, status, submit_us, launch_us, done_us)."""
+    def drive(self, queries, p, k, ef, arrival_us, with_stats=False):
+        """Submit on the given schedule, return (ids, dists, status, submit_us, launch_us, done_us)
+        (and the per-query stats as a STATS_DTYPE array when with_stats)."""
         queries = np.ascontiguousarray(queries, np.float32)
         n = queries.shape[0]
         p = np.ascontiguousarray(p, np.float32)
@@ -388,7 +399,11 @@ class Server:
         dists = raw[:, off_d:off_d + 4 * UHNSW_KMAX].copy().view(np.float32)
         status = np.array([r.status for r in res], np.int32)
         t = np.array([(r.submit_us, r.launch_us, r.done_us) for r in res], np.float64)
-        return ids, dists, status, t[:, 0], t[:, 1], t[:, 2]
+        if not with_stats:
+            return ids, dists, status, t[:, 0], t[:, 1], t[:, 2]
+        off_st = uhnsw_serve_result.stats.offset
+        st = raw[:, off_st:off_st + STATS_DTYPE.itemsize].copy().view(STATS_DTYPE).reshape(n)
+        return ids, dists, status, t[:, 0], t[:, 1], t[:, 2], st
 
     def stop(self):
         if getattr(self, "h", None):

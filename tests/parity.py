@@ -11,16 +11,18 @@ GPU result row is accepted when
     the K-th / (K+1)-th boundary of R u R' in some batch may also flip the
     stop decision (a different N_p); the GPU row must then still be the exact
     top-K of its own prefix C[0 : N_p] up to near ties.
-TIE_REL = 1e-5 covers twice the FP32 error bound of S_p derived for the
-kernels (accumulation over <= 64 terms per lane plus the pairwise combine,
-about 1.3e-6 for d <= 1024 at 16 lanes per row, and the v_log/v_exp term
-error of at most about 1.5e-6 at |delta| <= 255, p <= 2).
+TIE_REL = 1e-6 is the tie band of the stated parity target. The FP32 sums
+S_p of the kernels come out far closer than that: over every GPU parity case
+(about 8,000 rows, full size included) the widest FP64 gap an excused row
+needed was 5.0e-8, and 0.04 % of rows needed one. Every excused row reports
+the gap that explains it, so a test states its excused rate and the widest
+gap it needed.
 
 Distances: |d_gpu - d_64| <= DIST_REL * d_64 with d_64 the FP64 L_p distance.
 """
 import numpy as np
 
-TIE_REL = 1e-5
+TIE_REL = 1e-6
 DIST_REL = 1e-5
 
 
@@ -61,8 +63,23 @@ def alg1_fp64(S_c, ids_c, K, kappa, m):
     return ri, pos, gaps
 
 
-def check_row(base, q, p, K, kappa, m, c_ids, gpu_ids, gpu_dists, gpu_np, orc_ids, orc_np):
-    """Returns 'exact', 'excused' or raises AssertionError with a reason."""
+def _inversion_gap(S):
+    """Largest relative FP64 gap of a pair listed out of ascending order
+    (0 when S is ascending)."""
+    worst = 0.0
+    for i in range(len(S)):
+        for j in range(i + 1, len(S)):
+            if S[i] > S[j]:
+                worst = max(worst, (S[i] - S[j]) / max(abs(S[i]), 1e-300))
+    return worst
+
+
+def check_row(base, q, p, K, kappa, m, c_ids, gpu_ids, gpu_dists, gpu_np, orc_ids, orc_np, tie_rel=None):
+    """Returns ('exact', 0.0) or ('excused', gap), gap being the largest FP64
+    relative gap between two candidates whose order the GPU resolved
+    differently; raises AssertionError when a difference has no near tie
+    within tie_rel (default TIE_REL) to explain it."""
+    tie = TIE_REL if tie_rel is None else tie_rel
     nc = int((c_ids >= 0).sum())
     C = c_ids[:nc].astype(np.int64)
     nres = min(K, nc)
@@ -75,25 +92,33 @@ def check_row(base, q, p, K, kappa, m, c_ids, gpu_ids, gpu_dists, gpu_np, orc_id
         err = np.abs(gpu_dists[:nres].astype(np.float64) - d64)
         assert (err <= DIST_REL * np.maximum(d64, 1e-30)).all(), f"distance error {err.max() / d64.max():.2e}"
     if gpu_np == orc_np and list(g_ids) == list(orc_ids[:nres]):
-        return "exact"
+        return "exact", 0.0
     S_c = lp_sums64(base, q, C, p)
     _, _, gaps = alg1_fp64(S_c, C, K, kappa, m)
+    gap = 0.0
     if gpu_np != orc_np:
         hi = max(gpu_np, orc_np)
         nb_hi = (hi - nres + kappa - 1) // kappa if hi > nres else 0
-        assert any(g <= TIE_REL for g in gaps[:max(nb_hi, 1)]), f"N_p {gpu_np} != {orc_np} without a near tie"
+        flip = min(gaps[:max(nb_hi, 1)]) if gaps else np.inf
+        assert flip <= tie, f"N_p {gpu_np} != {orc_np} without a near tie (closest {flip:.2e})"
+        gap = max(gap, flip)
     # the GPU row is the exact top-K of its prefix, up to near ties
     pref = C[:gpu_np]
     sp, ip = _ranked(S_c[:gpu_np], pref)
     want = ip[:nres]
     got_S = lp_sums64(base, q, g_ids, p)
-    assert (np.diff(got_S) >= -TIE_REL * np.abs(got_S[1:])).all(), "GPU row not ascending"
-    if set(g_ids.tolist()) != set(want.tolist()):
+    inv = _inversion_gap(got_S)
+    assert inv <= tie, f"GPU row out of FP64 order by {inv:.2e}"
+    gap = max(gap, inv)
+    wset = set(want.tolist())
+    if set(g_ids.tolist()) != wset:
         # a member may differ only if it ties the boundary
         kth = sp[nres - 1]
         for gi, gs in zip(g_ids, got_S):
-            if gi not in set(want.tolist()):
-                assert abs(gs - kth) <= TIE_REL * kth, f"id {gi} (S={gs}) not in prefix top-K (K-th {kth})"
+            if gi not in wset:
+                g_rel = abs(gs - kth) / max(kth, 1e-300)
+                assert g_rel <= tie, f"id {gi} (S={gs}) not in prefix top-K (K-th {kth}, gap {g_rel:.2e})"
+                gap = max(gap, g_rel)
     else:
-        np.testing.assert_allclose(np.sort(got_S), sp[:nres], rtol=TIE_REL)
-    return "excused"
+        np.testing.assert_allclose(np.sort(got_S), sp[:nres], rtol=tie)
+    return "excused", gap

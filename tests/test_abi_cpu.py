@@ -53,7 +53,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(lib.uhnsw_graph) == 12 + 4 + 8 + 32 * 8 * 4  # M..entry, pad, level ptr, 4 arrays
     # n, d (+pad), base, storage (+pad), two graphs, variant (+pad)
     assert ctypes.sizeof(lib.uhnsw_index) == 8 + 8 + 8 + 8 + 2 * ctypes.sizeof(lib.uhnsw_graph) + 8
-    assert lib.STATS_DTYPE.itemsize == 40
+    assert lib.STATS_DTYPE.itemsize == 44
 
 
 def test_struct_layouts_match_c(lib, tmp_path):
@@ -67,7 +67,9 @@ def test_struct_layouts_match_c(lib, tmp_path):
     fields = {"uhnsw_index": ["n", "d", "base", "storage", "graphs", "variant"],
               "uhnsw_params": [f for f, _ in lib.uhnsw_params._fields_],
               "uhnsw_graph": ["M", "max_level", "entry_point", "level", "n_nodes", "nodes", "row_ptr", "col"],
-              "uhnsw_serve_config": [f for f, _ in lib.uhnsw_serve_config._fields_]}
+              "uhnsw_serve_config": [f for f, _ in lib.uhnsw_serve_config._fields_],
+              "uhnsw_stats": [f for f, _ in lib.uhnsw_stats._fields_],
+              "uhnsw_serve_result": [f for f, _ in lib.uhnsw_serve_result._fields_]}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "uhnsw.h"', "int main(void) {"]
     for st, fl in fields.items():
         lines.append(f'printf("{st} size %zu\\n", sizeof({st}));')

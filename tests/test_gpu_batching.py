@@ -200,3 +200,42 @@ def test_concurrent_streams(torch_cuda, ctxb, wl1):
             st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(50)
             np.testing.assert_array_equal(st["n_p"], r[2]["n_p"])
             np.testing.assert_array_equal(st["n_exp"], r[2]["n_exp"])
+
+
+def test_graph_recaptured_after_scratch_grows(torch_cuda, ctxb, wl1):
+    """A captured launch bakes in the per-stream scratch addresses (default
+    stats, the cost-ordering pre-pass arrays). An uncaptured search of more
+    queries on the same stream reallocates that scratch; the next captured
+    search with the first call's arguments must capture again rather than
+    replay into freed memory, and give the same results."""
+    from paper_2605_02030_amd import uhnsw
+
+    torch = torch_cuda
+    wl, _, _ = wl1
+    dev = torch.device("cuda:0")
+    p, k, ef = _mixed(wl, seed=37)
+    tq = torch.from_numpy(wl.queries).to(dev)
+    tp, tk, te = (torch.from_numpy(x).to(dev) for x in (p, k, ef))
+    half = 50
+    ids = torch.empty((half, 100), dtype=torch.int64, device=dev)
+    dists = torch.empty((half, 100), dtype=torch.float32, device=dev)
+    big_ids = torch.empty((wl.nq, 100), dtype=torch.int64, device=dev)
+    big_dists = torch.empty((wl.nq, 100), dtype=torch.float32, device=dev)
+    prm_g = uhnsw.default_params(fused=1, persistent=2, graph=1)  # stats left to the library's scratch
+    prm_e = uhnsw.default_params(fused=1, persistent=2)
+    ref = run_device(torch, ctxb, wl.queries[:half], p[:half], k[:half], ef[:half], 100, 256, params=prm_e)
+    before = ctxb.graph_captures()
+    ctxb.search_device(tq[:half], tp[:half], tk[:half], te[:half], 100, 256, ids, dists, params=prm_g)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ids.cpu().numpy(), ref[0])
+    assert ctxb.graph_captures() == before + 1
+    # a bigger uncaptured search on the same stream grows (moves) the scratch
+    ctxb.search_device(tq, tp, tk, te, 100, 256, big_ids, big_dists, params=prm_e)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        ids.fill_(-7)
+        ctxb.search_device(tq[:half], tp[:half], tk[:half], te[:half], 100, 256, ids, dists, params=prm_g)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ids.cpu().numpy(), ref[0])
+        np.testing.assert_array_equal(dists.cpu().numpy(), ref[1])
+    assert ctxb.graph_captures() == before + 2  # captured again once, then replayed

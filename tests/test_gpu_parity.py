@@ -1,6 +1,7 @@
 """GPU parity: the HIP query path (through the C-ABI) against the oracle, on
 the same seeded inputs. C must match bit for bit; top-K and N_p follow the
 near-tie rule of tests/parity.py; distances within 1e-5 of FP64."""
+import os
 import sys
 
 import numpy as np
@@ -61,7 +62,13 @@ def run_device(torch, ctx, queries, p, k, ef, k_max, ef_max, params=None, c_stri
 
 
 def compare(base, G1, G2, D, queries, p, k, ef, gpu, g, v, w=1, tau=0.92, kappa_param=0, t_param=0,
-            max_excused=0.05, cutoff=1.4, variant=oracle.VARIANT_STD):
+            max_excused=0.01, cutoff=1.4, variant=oracle.VARIANT_STD, label=None):
+    """The GPU results `gpu` = (ids, dists, stats, cand_ids, cand_keys) against
+    the oracle run on the same inputs: C, graph choice, descent end, |C| and
+    expansion counts bit-exact; every top-K row exact or excused by a near
+    tie (tests/parity.py). Prints the excused rate and the widest FP64 gap an
+    excuse needed; at most max_excused of the rows (at least one) may be
+    excused. Returns the number of excused rows."""
     ids, dists, st, cid, ckey = gpu
     nq = len(p)
     prm = oracle.Params(g=g, v=v, w=w, tau=tau, kappa=kappa_param, t_param=t_param, cutoff=cutoff,
@@ -79,14 +86,20 @@ def compare(base, G1, G2, D, queries, p, k, ef, gpu, g, v, w=1, tau=0.92, kappa_
     np.testing.assert_array_equal(ckey, o["c_keys"])
     assert (st["flags"] == 0).all()
     # verification
-    n_exc = 0
+    gaps = []
     for i in range(nq):
         K = int(k[i])
         kappa = kappa_param or max(K, 2)
         m = oracle.m_of(tau, K)
-        r = check_row(base, queries[i], p[i], K, kappa, m, cid[i], ids[i], dists[i], int(st["n_p"][i]),
-                      o["ids"][i], int(ost["n_p"][i]))
-        n_exc += r == "excused"
+        r, gap = check_row(base, queries[i], p[i], K, kappa, m, cid[i], ids[i], dists[i], int(st["n_p"][i]),
+                           o["ids"][i], int(ost["n_p"][i]))
+        if r == "excused":
+            gaps.append((i, float(p[i]), K, gap))
+    n_exc = len(gaps)
+    name = label or os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0]
+    widest = max((x[3] for x in gaps), default=0.0)
+    _say(f"parity {name}: {nq} rows, {n_exc} excused ({n_exc / max(nq, 1):.2%}), widest gap {widest:.2e}"
+         + "".join(f"; q{i} p={pv:.3f} K={K} gap {gp:.2e}" for i, pv, K, gp in gaps[:8]))
     assert n_exc <= max(1, max_excused * nq), f"{n_exc} of {nq} rows excused"
     return n_exc
 

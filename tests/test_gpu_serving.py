@@ -59,7 +59,7 @@ def test_alone_vs_mix_vs_batch(torch_cuda, ctxs, wl1):
         # in a mix: Poisson arrivals at 200k/s
         rng = np.random.Generator(np.random.PCG64(42))
         arrival = np.cumsum(rng.exponential(1e6 / 200_000, len(p)))
-        ids, dists, status, t_sub, t_launch, t_done = srv.drive(q, p, k, ef, arrival)
+        ids, dists, status, t_sub, t_launch, t_done, st = srv.drive(q, p, k, ef, arrival, with_stats=True)
         info = srv.info()
     finally:
         srv.stop()
@@ -77,6 +77,17 @@ def test_alone_vs_mix_vs_batch(torch_cuda, ctxs, wl1):
         np.testing.assert_array_equal(dists[i, :k[i]], ref_d[i, :k[i]])
     lat = t_done - t_sub
     _say(f"latency p50 {np.percentile(lat, 50):.0f} us p99 {np.percentile(lat, 99):.0f} us")
+    # and against the oracle: the served rows and counters with C from a
+    # device launch of the same queries (C is not part of a served result)
+    import oracle
+    from test_gpu_parity import compare, run_device
+
+    _, g1, g2 = wl1
+    g, v = ctxs.layout()
+    _, _, _, cid, ckey = run_device(torch_cuda, ctxs, q, p, k, ef, 100, 128,
+                                    params=uhnsw.default_params(fused=1))
+    compare(wl.base, oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base), q, p, k, ef,
+            (ids[:, :100], dists[:, :100], st, cid, ckey), g, v, label="served Poisson mix")
 
 
 def test_admission_busy_and_budget(torch_cuda, ctxs, wl1):
