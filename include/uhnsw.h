@@ -253,6 +253,29 @@ int uhnsw_search_device(uhnsw_ctx *ctx, const float *queries, int64_t nq, const 
                         int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
                         float *cand_keys, int32_t c_stride, void *stream);
 
+/* uhnsw_search_device for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same search, arguments and results, but the call makes no device, pinned
+ * or host allocation and creates no HIP object. Its scratch (default stats
+ * when `stats` is NULL, the two-kernel form's candidate lists when
+ * cand_ids is NULL, the work counter, the ordering pre-pass arrays) is
+ * carved from one fixed region of UHNSW_NOALLOC_SCRATCH_BYTES per device,
+ * reserved when the library's code object loads and held until the process
+ * ends; the caller still passes inputs and outputs. Every call on one
+ * device shares that region and it keeps the last call's contents (what
+ * must start at zero is cleared by a kernel on `stream`), so calls that
+ * overlap on one device race: serialise them (one stream, or wait between
+ * streams). A search needs about nq x (44 + 20 + 4) bytes, plus
+ * nq x ef_max x 8 for the two-kernel form without caller-held candidate
+ * arrays; one that needs more than the region fails.
+ * Errors: EINVAL (as uhnsw_search_device; also prm->graph or prm->timing
+ * set, or scratch above the region), ESTATE, EDEVICE. */
+#define UHNSW_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int uhnsw_search_device_noalloc(uhnsw_ctx *ctx, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                                const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm,
+                                int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats,
+                                int32_t *cand_ids, float *cand_keys, int32_t c_stride, void *stream);
+
 /* Batching form: pick execution knobs for this index and query mix by
  * timing the search on the given device queries (same arrays and limits as
  * uhnsw_search_device): visited-cache slots, waves per block, the schedule

@@ -68,6 +68,7 @@ struct GraphDev {
 struct uhnsw_ctx {
     int device = 0;
     int num_cus = 0;
+    void *noalloc = nullptr;  // the device's fixed scratch region (noalloc_scratch)
     hipStream_t stream = nullptr;
     bool loaded = false;
     bool failed = false;
@@ -552,8 +553,10 @@ int uhnsw_create(int device, uhnsw_ctx **out) {
     c->device = device;
     if ((e = hipSetDevice(device)) != hipSuccess ||
         (e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+        (e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = noalloc_scratch(device, &c->noalloc)) != hipSuccess) {
         g_create_error = std::string("device setup: ") + hipGetErrorString(e);
+        if (c->stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return UHNSW_EDEVICE;
     }
@@ -758,13 +761,27 @@ int uhnsw_last_timing(const uhnsw_ctx *c_, float *walk_ms, float *verify_ms) {
     return UHNSW_OK;
 }
 
-// One search enqueued on `stream` with the scratch set S (the set of the
-// stream the work finally runs on; under capture `stream` is the capture
-// stream).
+// (S is the set of the stream the work finally runs on; under capture
+// `stream` is the capture stream.)
+// Scratch of one search besides the caller's outputs: default stats, the
+// two-kernel path's candidate lists, the work counter, the pre-pass arrays.
+struct Scratch {
+    uhnsw_stats *stats = nullptr;
+    int32_t *cand_ids = nullptr, *ncand = nullptr, *counter = nullptr;
+    float *cand_keys = nullptr;
+    int32_t *o_entry = nullptr, *o_dnb = nullptr, *o_order = nullptr, *o_misc = nullptr;
+    float *o_ekey = nullptr, *o_dist = nullptr;
+};
+
+// One search enqueued on `stream`. Scratch comes from the stream's set S
+// (allocated or grown on demand), or, when `fixed` is given (S is then
+// null), is carved from that device region of `fixed_bytes` bytes: no
+// allocation, no events, no graph capture.
 static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries, int64_t nq, const float *p,
                      const int32_t *k, const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
                      int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
-                     float *cand_keys, int32_t c_stride, void *stream) {
+                     float *cand_keys, int32_t c_stride, void *stream, void *fixed = nullptr,
+                     size_t fixed_bytes = 0) {
     if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
     if (nq < 0 || nq > INT32_MAX) return fail(c, UHNSW_EINVAL, "nq=%lld outside [0, 2^31)", (long long)nq);
@@ -831,48 +848,92 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     a.k_stride = k_stride;
     a.counter = nullptr;
     a.order = nullptr;
-    if (stats) {
-        a.stats = stats;
-    } else {
-        HIP_OR_FAIL(c, ensure_scratch(c, S->stats, (size_t)nq * sizeof(uhnsw_stats)));
-        a.stats = S->stats.as<uhnsw_stats>();
-    }
-    if (prm.fused) {
-        a.cand_ids = cand_ids;  // C stays in LDS unless the caller asks for it
-        a.cand_keys = cand_keys;
-        a.c_stride = cand_ids ? c_stride : 0;
-        a.ncand = nullptr;
-    } else {
-        const int32_t cs = cand_ids ? c_stride : ef_max;
-        if (!cand_ids) {
-            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_ids, (size_t)nq * cs * 4));
-            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_keys, (size_t)nq * cs * 4));
-        }
-        HIP_OR_FAIL(c, ensure_scratch(c, S->ncand, (size_t)nq * 4));
-        a.cand_ids = cand_ids ? cand_ids : S->cand_ids.as<int32_t>();
-        a.cand_keys = cand_ids ? cand_keys : S->cand_keys.as<float>();
-        a.c_stride = cs;
-        a.ncand = S->ncand.as<int32_t>();
-    }
     const bool ordered = prm.persistent >= 2;
     const bool counted = prm.persistent == 1 || prm.persistent == 2;  // 3: ordered static grid
-    if (counted) HIP_OR_FAIL(c, ensure_scratch(c, S->counter, 4));
+    const int32_t cs = prm.fused ? (cand_ids ? c_stride : 0) : (cand_ids ? c_stride : ef_max);
+    const bool own_cand = !prm.fused && !cand_ids;
+    Scratch sc;
+    if (fixed) {
+        if (prm.graph || prm.timing)
+            return fail(c, UHNSW_EINVAL, "graph capture and timing need allocations: not in this entry point");
+        // carve the region in 256-byte aligned pieces, in a fixed order
+        size_t off = 0;
+        auto take = [&](size_t bytes) -> void * {
+            off = (off + 255) & ~(size_t)255;
+            void *q = static_cast<char *>(fixed) + off;
+            off += bytes;
+            return q;
+        };
+        const size_t q4 = (size_t)nq * 4;
+        if (!stats) sc.stats = static_cast<uhnsw_stats *>(take((size_t)nq * sizeof(uhnsw_stats)));
+        if (own_cand) {
+            sc.cand_ids = static_cast<int32_t *>(take((size_t)nq * cs * 4));
+            sc.cand_keys = static_cast<float *>(take((size_t)nq * cs * 4));
+        }
+        if (!prm.fused) sc.ncand = static_cast<int32_t *>(take(q4));
+        if (counted) sc.counter = static_cast<int32_t *>(take(4));
+        if (ordered) {
+            sc.o_entry = static_cast<int32_t *>(take(q4));
+            sc.o_ekey = static_cast<float *>(take(q4));
+            sc.o_dnb = static_cast<int32_t *>(take(q4));
+            sc.o_dist = static_cast<float *>(take(q4));
+            sc.o_order = static_cast<int32_t *>(take(q4));
+            sc.o_misc = static_cast<int32_t *>(take((6 + 2 * kOrderBuckets) * 4));
+        }
+        if (off > fixed_bytes)
+            return fail(c, UHNSW_EINVAL,
+                        "this search needs %zu bytes of scratch, above the fixed region's %zu (fewer queries, a "
+                        "smaller ef_max, the fused kernel or caller-held stats need less)",
+                        off, fixed_bytes);
+    } else {
+        const size_t q4 = (size_t)nq * 4;
+        if (!stats) {
+            HIP_OR_FAIL(c, ensure_scratch(c, S->stats, (size_t)nq * sizeof(uhnsw_stats)));
+            sc.stats = S->stats.as<uhnsw_stats>();
+        }
+        if (own_cand) {
+            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_ids, (size_t)nq * cs * 4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->cand_keys, (size_t)nq * cs * 4));
+            sc.cand_ids = S->cand_ids.as<int32_t>();
+            sc.cand_keys = S->cand_keys.as<float>();
+        }
+        if (!prm.fused) {
+            HIP_OR_FAIL(c, ensure_scratch(c, S->ncand, q4));
+            sc.ncand = S->ncand.as<int32_t>();
+        }
+        if (counted) {
+            HIP_OR_FAIL(c, ensure_scratch(c, S->counter, 4));
+            sc.counter = S->counter.as<int32_t>();
+        }
+        if (ordered) {
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_entry, q4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_ekey, q4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_dnb, q4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_dist, q4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_order, q4));
+            HIP_OR_FAIL(c, ensure_scratch(c, S->o_misc, (6 + 2 * kOrderBuckets) * 4));
+            sc.o_entry = S->o_entry.as<int32_t>();
+            sc.o_ekey = S->o_ekey.as<float>();
+            sc.o_dnb = S->o_dnb.as<int32_t>();
+            sc.o_dist = S->o_dist.as<float>();
+            sc.o_order = S->o_order.as<int32_t>();
+            sc.o_misc = S->o_misc.as<int32_t>();
+        }
+    }
+    a.stats = stats ? stats : sc.stats;
+    a.cand_ids = cand_ids ? cand_ids : sc.cand_ids;  // fused: C stays in LDS unless the caller asks for it
+    a.cand_keys = cand_ids ? cand_keys : sc.cand_keys;
+    a.c_stride = cs;
+    a.ncand = sc.ncand;
     OrderArgs oa{};
     if (ordered) {
-        const size_t q4 = (size_t)nq * 4;
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_entry, q4));
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_ekey, q4));
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_dnb, q4));
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_dist, q4));
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_order, q4));
-        HIP_OR_FAIL(c, ensure_scratch(c, S->o_misc, (6 + 2 * kOrderBuckets) * 4));
-        oa.entry = S->o_entry.as<int32_t>();
-        oa.ekey = S->o_ekey.as<float>();
-        oa.dnb = S->o_dnb.as<int32_t>();
-        oa.dist = S->o_dist.as<float>();
-        oa.gsum = S->o_misc.as<float>();
-        oa.bcnt = S->o_misc.as<int32_t>() + 6;
-        oa.order = S->o_order.as<int32_t>();
+        oa.entry = sc.o_entry;
+        oa.ekey = sc.o_ekey;
+        oa.dnb = sc.o_dnb;
+        oa.dist = sc.o_dist;
+        oa.gsum = reinterpret_cast<float *>(sc.o_misc);
+        oa.bcnt = sc.o_misc + 6;
+        oa.order = sc.o_order;
     }
 
     // the kernels of one search, in stream order
@@ -892,7 +953,7 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
             }
         if (!found) {
             HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp, pl.wpb * kWave, lds_block));
-            c->occ.push_back({kp, pl.wpb * kWave, lds_block, per_cu});
+            if (!fixed) c->occ.push_back({kp, pl.wpb * kWave, lds_block, per_cu});
         }
         per_cu = std::max(per_cu, 1);
         if (prm.waves_per_cu > 0) per_cu = std::min(per_cu, std::max(1, prm.waves_per_cu / pl.wpb));
@@ -902,12 +963,12 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         hipError_t e = hipSuccess;
         SearchArgs b = a;
         if (counted) {
-            b.counter = S->counter.as<int32_t>();
+            b.counter = sc.counter;
             if ((e = launch_fill_i32(b.counter, 0, 1, st)) != hipSuccess) return e;
         }
         if (timed && (e = hipEventRecord(S->ev[0], st)) != hipSuccess) return e;
         if (ordered) {  // descent pre-pass, then the likely-long queries first
-            if ((e = launch_fill_i32(S->o_misc.as<int32_t>(), 0, 6 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
+            if ((e = launch_fill_i32(sc.o_misc, 0, 6 + 2 * kOrderBuckets, st)) != hipSuccess) return e;
             if ((e = launch_order(b, oa, c->layout, st)) != hipSuccess) return e;
             b.order = oa.order;
             b.entry = oa.entry;
@@ -931,6 +992,10 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
         return hipSuccess;
     };
 
+    if (fixed) {
+        HIP_OR_FAIL(c, enqueue(s, false));
+        return UHNSW_OK;
+    }
     S->timed = prm.timing != 0;
     S->split = S->timed && !prm.graph;
     c->last_set = S;
@@ -1015,6 +1080,16 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
     if (int r = stream_set(c, reinterpret_cast<hipStream_t>(stream), &S)) return r;
     return search_on(c, S, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists, stats, cand_ids,
                      cand_keys, c_stride, stream);
+}
+
+int uhnsw_search_device_noalloc(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                                const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                                int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats,
+                                int32_t *cand_ids, float *cand_keys, int32_t c_stride, void *stream) {
+    if (!c) return UHNSW_EINVAL;
+    if (!c->noalloc) return fail(c, UHNSW_ESTATE, "no fixed scratch region on device %d", c->device);
+    return search_on(c, nullptr, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists, stats,
+                     cand_ids, cand_keys, c_stride, stream, c->noalloc, kNoAllocScratchBytes);
 }
 
 int uhnsw_probe_gather(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {

@@ -107,6 +107,12 @@ struct OrderArgs {
     int32_t *order;   // [nq] out
 };
 
+// The fixed scratch region of the entry point that allocates nothing: its
+// size, and its device address on `device` (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)UHNSW_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void **out);
+
 // Launchers (uhnsw_kernels.hip). Return the HIP status of the launch.
 hipError_t launch_walk(const SearchArgs &a, int layout, int grid, hipStream_t s);
 hipError_t launch_verify(const SearchArgs &a, int layout, int grid, hipStream_t s);

@@ -3,9 +3,39 @@
 // ordering pre-pass kernels, the utility kernels and the launchers. The
 // walk, fused and descent kernels are instantiated per (storage, index
 // variant) in uhnsw_walk_part.hip; all device code is in uhnsw_device.h.
+#include <mutex>
+
 #include "uhnsw_device.h"
 
 namespace uhnsw {
+
+// ------------------------------------------------ fixed scratch region
+// The scratch of uhnsw_search_device_noalloc: one region per device,
+// reserved when the code object loads and held until the process ends.
+// Host code must not use the array's name as an address (it is a host-side
+// stand-in); noalloc_scratch returns the device address, looked up once per
+// device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(int device, void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
 
 // One workgroup: per graph the sum and count of entry distances, and the
 // sum and count of ef, over all searchable queries (fixed order, no atomics).

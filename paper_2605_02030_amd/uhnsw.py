@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libuhnsw.so")
 UHNSW_OK, UHNSW_EINVAL, UHNSW_ENOMEM, UHNSW_EDEVICE = 0, -1, -2, -3
 UHNSW_ESTATE, UHNSW_EIO, UHNSW_EBUSY, UHNSW_EUNSUPPORTED = -4, -5, -6, -7
 UHNSW_MAX_LAYERS, UHNSW_KMAX, UHNSW_EFMAX, UHNSW_DMAX = 32, 256, 2048, 1024
+UHNSW_NOALLOC_SCRATCH_BYTES = 64 << 20
 STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
@@ -27,7 +28,7 @@ EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
            "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files", "uhnsw_check_index",
-           "uhnsw_check_index_files", "uhnsw_reset", "uhnsw_last_timing_split")
+           "uhnsw_check_index_files", "uhnsw_reset", "uhnsw_last_timing_split", "uhnsw_search_device_noalloc")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -94,6 +95,8 @@ uhnsw_reset = _sig("uhnsw_reset", ctypes.c_int, [_P])
 uhnsw_search = _sig("uhnsw_search", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _P, _I32, _P, _P, _P])
 uhnsw_search_device = _sig("uhnsw_search_device", ctypes.c_int,
                            [_P, _P, _I64, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _I32, _P])
+uhnsw_search_device_noalloc = _sig("uhnsw_search_device_noalloc", ctypes.c_int,
+                                   [_P, _P, _I64, _P, _P, _P, _I32, _I32, _P, _I32, _P, _P, _P, _P, _P, _I32, _P])
 uhnsw_get_layout = _sig("uhnsw_get_layout", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 uhnsw_autotune = _sig("uhnsw_autotune", ctypes.c_int, [_P, _P, _I64, _P, _P, _P, _I32, _I32, _I32, _P, _P])
 uhnsw_graph_captures = _sig("uhnsw_graph_captures", ctypes.c_int, [_P, ctypes.POINTER(_I64)])
@@ -278,6 +281,24 @@ class Context:
             self.h, queries.data_ptr(), nq, p.data_ptr(), k.data_ptr(), ef.data_ptr(), int(k_max), int(ef_max),
             prm, ks, ids.data_ptr(), dists.data_ptr(), stats.data_ptr() if stats is not None else None,
             cand_ids.data_ptr() if cand_ids is not None else None,
+            cand_keys.data_ptr() if cand_keys is not None else None, cs, stream))
+
+    def search_device_noalloc(self, queries, p, k, ef, k_max: int, ef_max: int, ids, dists, stats=None,
+                              cand_ids=None, cand_keys=None, params: uhnsw_params | None = None, stream=None):
+        """search_device without any allocation (scratch from the device's
+        fixed region; see include/uhnsw.h)."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        cs = cand_ids.shape[1] if cand_ids is not None else 0
+        prm = ctypes.byref(params) if params is not None else None
+        self._check(uhnsw_search_device_noalloc(
+            self.h, queries.data_ptr(), queries.shape[0], p.data_ptr(), k.data_ptr(), ef.data_ptr(), int(k_max),
+            int(ef_max), prm, ids.shape[1], ids.data_ptr(), dists.data_ptr(),
+            stats.data_ptr() if stats is not None else None, cand_ids.data_ptr() if cand_ids is not None else None,
             cand_keys.data_ptr() if cand_keys is not None else None, cs, stream))
 
     def autotune(self, queries, p, k, ef, k_max: int, ef_max: int, params: uhnsw_params | None = None,
