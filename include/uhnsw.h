@@ -336,6 +336,48 @@ int uhnsw_last_timing(const uhnsw_ctx *ctx, float *walk_ms, float *verify_ms);
  * replayed from a captured hipGraph has no split: ESTATE. */
 int uhnsw_last_timing_split(const uhnsw_ctx *ctx, float *prepass_ms, float *walk_ms, float *verify_ms);
 
+/* ------------------------------------------------- graph construction
+ * GPU construction of one HNSW base graph (HNSW's layered graph, Sec. 2.2;
+ * building G1 and G2 is the method's up-front cost, Sec. 4.4.3, Table 3)
+ * under metric 1 (L1, for G1 and G_1), 2 (squared L2, for G2) or 3
+ * (sum sqrt|x - q|, for G_0.5), on the context's device:
+ *   - node levels floor(-ln(U_v) / ln M) with U_v in (0, 1] from
+ *     splitmix64(seed ^ v * 0x9E3779B97F4A7C15) (top 53 bits + 1) / 2^53,
+ *     capped at 30;
+ *   - insertion in id order, in batches of clamp(nodes in the graph / 64,
+ *     1, batch_max) that are planned against the graph frozen at the batch
+ *     start: greedy descent above the node's level, a best-first search
+ *     with ef_construction on each of its layers, M neighbours per layer by
+ *     the diversity heuristic (keep e unless a kept r has d(e, r) <
+ *     d(node, e)); then reverse links grouped by target, in ascending
+ *     source id, a full list (2M on layer 0, M above) re-selected by the
+ *     same heuristic;
+ *   - distances in FP32 in one order: element j summed by lane (j / 4) mod
+ *     16 of 16 lanes in ascending j (L2 by fused multiply-add), the lanes
+ *     combined pairwise (o = 8, 4, 2, 1).
+ * The result is deterministic and identical to the CPU input builder's
+ * (same steps, same distance order) for the same arguments.
+ * base: host, n x d FP32 row-major (copied; the context's loaded index is
+ * not used or changed). *out receives a graph the caller frees with
+ * uhnsw_built_graph_free.
+ * Errors: EINVAL (NULL, n < 1, d outside [1, UHNSW_DMAX], metric, M outside
+ * [2, 31], ef_construction outside [1, UHNSW_EFMAX], batch_max outside
+ * [1, 65536], a non-finite value), EUNSUPPORTED (upper layers above 2^31
+ * ids), ENOMEM, EDEVICE; the message is uhnsw_last_error(ctx). */
+#define UHNSW_METRIC_L1 1
+#define UHNSW_METRIC_L2 2
+#define UHNSW_METRIC_L05 3
+typedef struct uhnsw_built_graph uhnsw_built_graph;
+int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, int32_t M,
+                      int32_t ef_construction, uint64_t seed, int32_t batch_max, uhnsw_built_graph **out);
+
+/* The built graph as a uhnsw_graph (per-layer CSR; pointers into *g, valid
+ * until uhnsw_built_graph_free), ready for uhnsw_index.graphs[]; the build's
+ * wall time in seconds and its batch count (either may be NULL). */
+int uhnsw_built_graph_view(const uhnsw_built_graph *g, uhnsw_graph *out, double *build_seconds,
+                           int64_t *batches);
+void uhnsw_built_graph_free(uhnsw_built_graph *g);
+
 /* ------------------------------------------------------------ serving form
  * Continuous batching over the loaded index. Queries are admitted into
  * slots as they arrive; a dispatcher thread launches whatever is pending as

@@ -28,7 +28,8 @@ def _units():
     instantiations build in parallel."""
     hip = ["-x", "hip"]
     units = [("uhnsw_kernels.hip", "uhnsw_kernels", hip + DEVICE_FLAGS),
-             ("uhnsw_probe.hip", "uhnsw_probe", hip + DEVICE_FLAGS)]
+             ("uhnsw_probe.hip", "uhnsw_probe", hip + DEVICE_FLAGS),
+             ("uhnsw_build.hip", "uhnsw_build", hip + DEVICE_FLAGS)]
     for s in range(3):
         for e in range(2):
             units.append(("uhnsw_walk_part.hip", f"uhnsw_walk_part_{s}_{e}",

@@ -136,6 +136,7 @@ int ctx_variant(const uhnsw_ctx *c) { return c->variant; }
 void ctx_servers(uhnsw_ctx *c, int delta) { c->servers += delta; }
 int ctx_dim(const uhnsw_ctx *c) { return c->d; }
 int ctx_device(const uhnsw_ctx *c) { return c->device; }
+void ctx_set_error(uhnsw_ctx *c, const char *msg) { c->err = msg; }
 }  // namespace uhnsw
 
 namespace {

@@ -137,5 +137,6 @@ int ctx_variant(const uhnsw_ctx *c);
 void ctx_servers(uhnsw_ctx *c, int delta);  // servers running on the context
 bool p_in_range(int variant, float p);  // the index variant's p range
 int ctx_device(const uhnsw_ctx *c);
+void ctx_set_error(uhnsw_ctx *c, const char *msg);  // the message uhnsw_last_error returns
 
 }  // namespace uhnsw

@@ -22,13 +22,15 @@ STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
 VARIANT_STD, VARIANT_EXT = 0, 1
+METRIC_L1, METRIC_L2, METRIC_L05 = 1, 2, 3
 
 EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
            "uhnsw_autotune", "uhnsw_graph_captures", "uhnsw_serve_default_config", "uhnsw_serve_start",
            "uhnsw_serve_submit", "uhnsw_serve_poll", "uhnsw_serve_info", "uhnsw_serve_drive", "uhnsw_serve_stop",
            "uhnsw_probe_gather", "uhnsw_probe_transcendental", "uhnsw_load_graph_files", "uhnsw_check_index",
-           "uhnsw_check_index_files", "uhnsw_reset", "uhnsw_last_timing_split", "uhnsw_search_device_noalloc")
+           "uhnsw_check_index_files", "uhnsw_reset", "uhnsw_last_timing_split", "uhnsw_search_device_noalloc",
+           "uhnsw_build_graph", "uhnsw_built_graph_view", "uhnsw_built_graph_free")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_02030_amd.build` "
@@ -122,6 +124,13 @@ uhnsw_check_index = _sig("uhnsw_check_index", ctypes.c_int, [_P, ctypes.c_char_p
 uhnsw_check_index_files = _sig("uhnsw_check_index_files", ctypes.c_int,
                                [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, _I32, _I32, ctypes.c_char_p,
                                 _I32])
+
+
+uhnsw_build_graph = _sig("uhnsw_build_graph", ctypes.c_int,
+                         [_P, _P, _I64, _I32, _I32, _I32, _I32, ctypes.c_uint64, _I32, ctypes.POINTER(_P)])
+uhnsw_built_graph_view = _sig("uhnsw_built_graph_view", ctypes.c_int,
+                              [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)])
+uhnsw_built_graph_free = _sig("uhnsw_built_graph_free", None, [_P])
 
 
 class UhnswError(RuntimeError):
@@ -359,6 +368,54 @@ class Context:
         a, w, v = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
         self._check(uhnsw_last_timing_split(self.h, ctypes.byref(a), ctypes.byref(w), ctypes.byref(v)))
         return a.value, w.value, v.value
+
+
+class BuiltLayer:
+    def __init__(self, nodes, row_ptr, col):
+        self.nodes, self.row_ptr, self.col = nodes, row_ptr, col
+
+
+class BuiltGraph:
+    """A graph made by uhnsw_build_graph, copied into numpy arrays (the
+    fields load_graphs reads: M, max_level, entry, levels, layers)."""
+
+    def __init__(self, view: uhnsw_graph, n: int, metric: int, seconds: float, batches: int):
+        self.metric, self.n, self.M = metric, n, int(view.M)
+        self.max_level, self.entry = int(view.max_level), int(view.entry_point)
+        self.seconds, self.batches = seconds, batches
+        self.levels = np.ctypeslib.as_array(ctypes.cast(view.level, ctypes.POINTER(ctypes.c_int8)), (n,)).copy()
+        self.layers = []
+        for l in range(self.max_level + 1):
+            nl = int(view.n_nodes[l])
+            rp = np.ctypeslib.as_array(ctypes.cast(view.row_ptr[l], ctypes.POINTER(_I64)), (nl + 1,)).copy()
+            ne = int(rp[-1])
+            col = np.ctypeslib.as_array(ctypes.cast(view.col[l], ctypes.POINTER(_I32)), (max(ne, 1),))[:ne].copy()
+            nodes = None
+            if l:
+                nodes = np.ctypeslib.as_array(ctypes.cast(view.nodes[l], ctypes.POINTER(_I32)), (nl,)).copy()
+            self.layers.append(BuiltLayer(nodes, rp, col))
+
+    @property
+    def M0(self) -> int:
+        return 2 * self.M
+
+
+def build_graph(ctx: "Context", base, metric: int, M: int = 16, ef_construction: int = 200, seed: int = 0,
+                batch_max: int = 1024) -> BuiltGraph:
+    """uhnsw_build_graph on ctx's device: one HNSW graph of `base` under
+    `metric` (METRIC_L1, METRIC_L2, METRIC_L05)."""
+    base = np.ascontiguousarray(base, np.float32)
+    n, d = base.shape
+    h = _P()
+    ctx._check(uhnsw_build_graph(ctx.h, base.ctypes.data, n, d, int(metric), int(M), int(ef_construction),
+                                 int(seed), int(batch_max), ctypes.byref(h)))
+    try:
+        view = uhnsw_graph()
+        sec, nb = ctypes.c_double(), _I64()
+        ctx._check(uhnsw_built_graph_view(h, ctypes.byref(view), ctypes.byref(sec), ctypes.byref(nb)))
+        return BuiltGraph(view, n, metric, sec.value, nb.value)
+    finally:
+        uhnsw_built_graph_free(h)
 
 
 class Server:

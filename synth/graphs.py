@@ -21,7 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hnsw_build.c")
 _LIB = os.path.join(_HERE, "_hnsw_build.so")
-BUILDER_VERSION = "hb1"
+BUILDER_VERSION = "hb2"
 
 _lib = None
 
@@ -30,7 +30,7 @@ def build_lib(force: bool = True) -> str:
     """Compile the builder into ``synth/_hnsw_build.so``."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
-        cmd = ["gcc", "-O3", "-mavx2", "-mfma", "-fopenmp", "-fPIC", "-shared",
+        cmd = ["gcc", "-O3", "-mavx2", "-mfma", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -45,7 +45,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.hb_build.restype = ctypes.c_void_p
         lib.hb_build.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int]
         lib.hb_max_level.restype = ctypes.c_int
         lib.hb_max_level.argtypes = [ctypes.c_void_p]
         lib.hb_entry.restype = ctypes.c_int32
@@ -123,19 +124,24 @@ def _load_file(path: str) -> Graph:
 
 def build_graph(base: np.ndarray, metric: int, M: int = 16, ef_construction: int = 200,
                 seed: int = 0, threads: int = 0, cache: bool = True,
-                digest: str | None = None, verbose: bool = False) -> Graph:
+                digest: str | None = None, verbose: bool = False, batch_max: int = 1024) -> Graph:
+    """The HNSW graph of `base` under `metric` (1 L1, 2 L2, 3 L0.5), built by
+    hnsw_build.c in insertion batches of at most `batch_max` nodes."""
     base = np.ascontiguousarray(base, dtype=np.float32)
     n, d = base.shape
     path = None
     if cache:
         if digest is None:
             digest = hashlib.sha256(base.tobytes()).hexdigest()
-        path = os.path.join(_cache_dir(), f"g_{_key(digest, metric, M, ef_construction, seed)}.npz")
+        key = _key(digest, metric, M, ef_construction, seed)
+        if batch_max != 1024:
+            key = _key(f"{digest}:b{batch_max}", metric, M, ef_construction, seed)
+        path = os.path.join(_cache_dir(), f"g_{key}.npz")
         if os.path.exists(path):
             return _load_file(path)
     lib = _load()
     t0 = time.time()
-    h = lib.hb_build(base.ctypes.data, n, d, metric, M, ef_construction, seed, threads, int(verbose))
+    h = lib.hb_build(base.ctypes.data, n, d, metric, M, ef_construction, seed, threads, int(verbose), batch_max)
     if not h:
         raise ValueError("hnsw build rejected its arguments")
     try:

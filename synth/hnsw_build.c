@@ -21,11 +21,12 @@
  * applies links: each new node's own lists, then the reverse links grouped
  * by target node (parallel over targets, each target's requests in
  * ascending source id). The graph is therefore identical for any thread
- * count. Batch size grows with the graph (1 while small, at most 1024).
+ * count. Batch size grows with the graph (the number of nodes already in
+ * it over 64, at least 1, at most batch_max; 1024 by default).
  *
- * Distances here are FP32 with 16 independent partial sums (fixed order, so
- * deterministic per binary). This file is an input generator: it shares no
- * code with the oracle or with the GPU library.
+ * Distances are FP32 in one fixed order (see dist_metric), independent of
+ * the compiler. This file is an input generator: it shares no code with the
+ * oracle or with the GPU library.
  */
 #include <math.h>
 #include <omp.h>
@@ -57,54 +58,43 @@ typedef struct {
 } hb_t;
 
 /* ---------------------------------------------------------------- distance */
-static float dist_l1(const float *a, const float *b, int d) {
-    float s[16];
-    for (int u = 0; u < 16; u++) s[u] = 0.0f;
-    int j = 0;
-    for (; j + 16 <= d; j += 16)
-        for (int u = 0; u < 16; u++) s[u] += fabsf(a[j + u] - b[j + u]);
-    float r = 0.0f;
-    for (; j < d; j++) r += fabsf(a[j] - b[j]);
-    for (int u = 0; u < 16; u++) r += s[u];
-    return r;
+/* One fixed FP32 order, so that any implementation following it gets the
+ * same bits (a GPU construction of these graphs is compared edge for edge
+ * with this builder): element j is accumulated by lane (j / 4) mod 16 of 16
+ * lanes, each lane in ascending j from +0 (L2 by fused multiply-add), then
+ * the lanes combine pairwise: for o = 8, 4, 2, 1, lane l < o takes
+ * s_l + s_{l+o}. Compiled with -ffp-contract=off. */
+#define HB_LANES 16
+#define HB_V 4
+
+static inline float term(int metric, float a, float b) {
+    const float t = a - b;
+    return metric == 1 ? fabsf(t) : sqrtf(fabsf(t));
 }
 
-static float dist_l2(const float *a, const float *b, int d) {
-    float s[16];
-    for (int u = 0; u < 16; u++) s[u] = 0.0f;
-    int j = 0;
-    for (; j + 16 <= d; j += 16)
-        for (int u = 0; u < 16; u++) {
-            float t = a[j + u] - b[j + u];
-            s[u] += t * t;
-        }
-    float r = 0.0f;
-    for (; j < d; j++) {
-        float t = a[j] - b[j];
-        r += t * t;
-    }
-    for (int u = 0; u < 16; u++) r += s[u];
-    return r;
-}
-
-/* sum sqrt|a - b|: the L0.5 distance's square root, ranked like it */
-static float dist_l05(const float *a, const float *b, int d) {
-    float s[16];
-    for (int u = 0; u < 16; u++) s[u] = 0.0f;
-    int j = 0;
-    for (; j + 16 <= d; j += 16)
-        for (int u = 0; u < 16; u++) s[u] += sqrtf(fabsf(a[j + u] - b[j + u]));
-    float r = 0.0f;
-    for (; j < d; j++) r += sqrtf(fabsf(a[j] - b[j]));
-    for (int u = 0; u < 16; u++) r += s[u];
-    return r;
+static float dist_metric(const float *a, const float *b, int d, int metric) {
+    float s[HB_LANES];
+    for (int l = 0; l < HB_LANES; l++) s[l] = 0.0f;
+    for (int c = 0; c < d; c += HB_LANES * HB_V)
+        for (int l = 0; l < HB_LANES; l++)
+            for (int e = 0; e < HB_V; e++) {
+                const int j = c + l * HB_V + e;
+                if (j >= d) break;
+                if (metric == 2) {
+                    const float t = a[j] - b[j];
+                    s[l] = fmaf(t, t, s[l]);
+                } else {
+                    s[l] = s[l] + term(metric, a[j], b[j]);
+                }
+            }
+    for (int o = HB_LANES / 2; o >= 1; o >>= 1)
+        for (int l = 0; l < o; l++) s[l] = s[l] + s[l + o];
+    return s[0];
 }
 
 static inline const float *vec(const hb_t *g, int32_t v) { return g->base + (int64_t)v * g->d; }
 
-static inline float dist(const hb_t *g, const float *a, const float *b) {
-    return g->metric == 1 ? dist_l1(a, b, g->d) : g->metric == 2 ? dist_l2(a, b, g->d) : dist_l05(a, b, g->d);
-}
+static inline float dist(const hb_t *g, const float *a, const float *b) { return dist_metric(a, b, g->d, g->metric); }
 
 static inline int32_t *nbrs(const hb_t *g, int32_t v, int l, int *cnt) {
     if (l == 0) {
@@ -348,8 +338,8 @@ static uint64_t splitmix64(uint64_t x) {
 
 /* ----------------------------------------------------------- public API */
 void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, uint64_t seed, int nthreads,
-               int verbose) {
-    if (n < 1 || d < 1 || metric < 1 || metric > 3 || M < 2 || M > 127 || efc < 1) return NULL;
+               int verbose, int batch_max) {
+    if (n < 1 || d < 1 || metric < 1 || metric > 3 || M < 2 || M > 127 || efc < 1 || batch_max < 1) return NULL;
     hb_t *g = (hb_t *)calloc(1, sizeof(hb_t));
     g->n = n;
     g->d = d;
@@ -381,7 +371,7 @@ void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, 
     ws_t *ws = (ws_t *)malloc(sizeof(ws_t) * (size_t)nthreads);
     for (int i = 0; i < nthreads; i++) ws_init(&ws[i], n);
 
-    const int BMAX = 1024;
+    const int BMAX = batch_max;
     plan_t *plans = (plan_t *)calloc(BMAX, sizeof(plan_t));
     for (int i = 0; i < BMAX; i++) {
         plans[i].ids = (int32_t *)malloc(sizeof(int32_t) * 32 * (size_t)M);
