@@ -57,10 +57,13 @@ EF_GRID = (32, 64, 128, 256)
 # the extended index's p near 0.2 needs a wider walk (oracle recall@10 at
 # ef 256 / 512: 0.89 / 0.95 on workload 7)
 EF_GRID_EXT = (128, 256, 384, 512)
-# workload -> n actually used: the serving form's 10M-row graphs are not built
-# here (about an hour of CPU per graph pair), a 1M-row index of the same
-# distribution stands in for it
+# --reduced: the serving form's workload at 1M rows (graphs from the CPU
+# builder's cache); by default it runs at its 10M rows with graphs built on
+# the GPU
 REDUCED_N = {5: 1_000_000}
+# efSearch grid of the secondary workloads' sweeps: through EFMAX, to state
+# the recall each input can reach
+EF_SWEEP = (32, 64, 128, 256, 512, 1024, 2048)
 TARGET_RECALL = 0.9
 
 
@@ -228,44 +231,53 @@ def method_bytes(wl, elem, gpu_st, counts, fused):
     return float(walk), float(up * wl.d * elem)
 
 
-def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000, 400_000), seconds=0.5,
-            max_queries=50_000, storage=None, k=None, k_max=10, label="BF16", variant=0):
+def serving(torch, uhnsw, wl, g1, g2, gt, ef, rates=(20_000, 50_000, 100_000, 200_000), seconds=5.0,
+            warmup_s=0.5, storage=None, k=None, k_max=10, label="BF16", variant=0, params=None):
     """Serving form: Poisson arrivals into the continuous-batching server.
-    Arrival i carries query i mod nq; each rate runs for `seconds` or
-    `max_queries` arrivals, whichever is fewer. `k` gives each query's K
-    (default: the workload's), `ef` one efSearch for all."""
+    Arrival i carries query i mod nq. Each offered rate runs `warmup_s` of
+    arrivals that are not counted, then `seconds` of measured arrivals:
+    achieved QPS over the measured arrivals' span, their p50 / p99 / p99.9
+    latency (completion minus scheduled arrival, queueing included). `k`
+    gives each query's K (default: the workload's), `ef` one efSearch for
+    all; admission slots follow the fused kernel's LDS plan."""
     ctx = uhnsw.Context(0)
     ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_BF16 if storage is None else storage, variant=variant)
     kq = wl.k if k is None else k
+    prm = params or uhnsw.default_params(beam_width=2, visited_slots=1024)
     out = []
-    pos_of = {int(q): i for i, q in enumerate(gt["qidx"])}
+    gt_row = np.full(wl.nq, -1, np.int64)
+    gt_row[gt["qidx"]] = np.arange(len(gt["qidx"]))
     for rate in rates:
-        n = min(max_queries, int(rate * seconds))
-        qi = np.arange(n) % wl.nq
+        n = int(rate * (seconds + warmup_s))
+        qi = (np.arange(n) % wl.nq).astype(np.int32)
         rng = np.random.Generator(np.random.PCG64(rate))
         arrival = np.cumsum(rng.exponential(1e6 / rate, n))
-        srv = uhnsw.Server(ctx, k_max=k_max, ef_max=ef,
-                           params=uhnsw.default_params(beam_width=2, visited_slots=1024))
+        srv = uhnsw.Server(ctx, k_max=k_max, ef_max=ef, params=prm)
         try:
-            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries[qi], wl.p[qi], kq[qi],
-                                                                    np.full(n, ef, np.int32), arrival)
+            ids, dists, status, t_sub, t_launch, t_done = srv.drive(wl.queries, wl.p[qi], kq[qi],
+                                                                    np.full(n, ef, np.int32), arrival, out_k=10,
+                                                                    qidx=qi)
             info = srv.info()
         finally:
             srv.stop()
-        lat_ms = (t_done - t_sub) / 1e3
-        span_s = (t_done.max() - arrival[0]) / 1e6
-        sel = [i for i in range(n) if int(qi[i]) in pos_of]
-        rec = float(np.mean([len(set(ids[i, :10].tolist()) & set(gt["ids"][pos_of[int(qi[i])]].tolist())) / 10
-                             for i in sel])) if sel else None
-        r = dict(offered_qps=rate, queries=n, achieved_qps=round(n / span_s, 1),
+        meas = arrival >= warmup_s * 1e6
+        lat_ms = (t_done - t_sub)[meas] / 1e3
+        span_s = (t_done[meas].max() - arrival[meas][0]) / 1e6
+        sel = np.flatnonzero(meas & (gt_row[qi] >= 0))
+        rec = float(np.mean([len(set(ids[i, :10].tolist()) & set(gt["ids"][gt_row[qi[i]]].tolist())) / 10
+                             for i in sel[:20000]])) if len(sel) else None
+        r = dict(offered_qps=rate, measured_queries=int(meas.sum()), measured_s=round(float(span_s), 3),
+                 warmup_queries=int((~meas).sum()), achieved_qps=round(float(meas.sum() / span_s), 1),
                  p50_ms=round(float(np.percentile(lat_ms, 50)), 3), p99_ms=round(float(np.percentile(lat_ms, 99)), 3),
+                 p999_ms=round(float(np.percentile(lat_ms, 99.9)), 3), mean_ms=round(float(lat_ms.mean()), 3),
                  recall_at_10=round(rec, 4) if rec is not None else None, batches=info["batches"],
-                 max_batches_in_flight=info["max_overlap"], errors=int((status != 0).sum()))
+                 max_batches_in_flight=info["max_overlap"], slots=info["slots"],
+                 waves_per_cu=info["waves_per_cu"], errors=int((status != 0).sum()))
         log("serving", json.dumps(r))
         out.append(r)
     ctx.close()
-    return dict(form=f"{label} walk, beam 2, fused launches on 2 streams, continuous batching", ef=ef,
-                k=sorted(set(int(x) for x in np.unique(kq))), rates=out)
+    return dict(form=f"{label} walk, beam {prm.beam_width}, fused launches on 2 streams, continuous batching",
+                ef=ef, k=sorted(set(int(x) for x in np.unique(kq))), rates=out)
 
 
 def _cpu_model():
@@ -352,10 +364,27 @@ def lp_dist64(base, q, ids, p):
 def run_secondary(a, torch, uhnsw, sg, synth):
     """Workload 3 (precision form), 4 (batching form) or 5 (serving form, at
     a tenth of its size): one JSON line."""
-    wl = synth.make_workload(a.workload, n=REDUCED_N.get(a.workload))
-    log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq}")
+    t0 = time.time()
+    wl = synth.make_workload(a.workload, n=REDUCED_N.get(a.workload) if a.reduced else None)
+    log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq} ({time.time() - t0:.1f}s)")
     gt = gt_for(wl)
-    g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+    out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries": wl.nq, "forms": {}}
+    if wl.n > 2_000_000:  # too large for the CPU builder: construct G1 and G2 on the GPU
+        bctx = uhnsw.Context(0)
+        graphs = []
+        for metric in (sg.METRIC_L1, sg.METRIC_L2):
+            g = uhnsw.build_graph(bctx, wl.base, metric, M=wl.M, ef_construction=wl.ef_construction,
+                                  seed=wl.graph_seed)
+            log(f"GPU build metric {metric}: {g.seconds:.1f}s, {g.batches} batches, max level {g.max_level}")
+            graphs.append(g)
+        bctx.close()
+        g1, g2 = graphs
+        out["graph_build"] = {"where": "GPU (uhnsw_build_graph)", "M": wl.M,
+                              "efConstruction": wl.ef_construction,
+                              "seconds": {"G1": round(g1.seconds, 1), "G2": round(g2.seconds, 1)},
+                              "batches": g1.batches}
+    else:
+        g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
     dev = torch.device("cuda:0")
     q = torch.from_numpy(wl.queries).to(dev)
     p = torch.from_numpy(wl.p).to(dev)
@@ -364,7 +393,6 @@ def run_secondary(a, torch, uhnsw, sg, synth):
     ids = torch.empty((wl.nq, kmax), dtype=torch.int64, device=dev)
     dists = torch.empty((wl.nq, kmax), dtype=torch.float32, device=dev)
     stats = torch.zeros((wl.nq, uhnsw.STATS_WORDS), dtype=torch.int32, device=dev)
-    out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries": wl.nq, "forms": {}}
 
     spare = (torch.empty_like(ids), torch.empty_like(dists), torch.empty_like(stats))
     streams = (torch.cuda.Stream(), torch.cuda.Stream())
@@ -396,26 +424,57 @@ def run_secondary(a, torch, uhnsw, sg, synth):
             err = max(err, float(np.max(np.abs(dists_np[i, :kk] - d64) / d64)))
         return rec, err
 
+    def sweep_ef(ctx, prm_kw, label, grid=EF_SWEEP):
+        """ef_i = max(k_i, E) over the grid (stops after the first E reaching
+        the target recall): QPS of one launch of all queries, recall@10."""
+        rows = []
+        for E in grid:
+            ef_np = np.maximum(wl.k, E).astype(np.int32)
+            ef_t = torch.from_numpy(ef_np).to(dev)
+            dt = timed_run(ctx, ef_t, int(ef_np.max()), uhnsw.default_params(**prm_kw), max(3, a.steps // 4))
+            rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
+            st = stats.cpu().numpy().view(uhnsw.STATS_DTYPE).reshape(wl.nq)
+            rows.append(dict(E=E, qps=round(wl.nq / dt, 1), recall_at_10=round(rec, 4), max_rel_dist_err=err,
+                             mean_n_b=round(float(st["n_b"].mean()), 1)))
+            log(label, json.dumps(rows[-1]))
+            if rec >= TARGET_RECALL:
+                break
+        return rows
+
     if a.workload == 5:
-        # the same index in batch mode for reference: one fused persistent launch, FP16 walk
-        ef_t = torch.from_numpy(wl.ef).to(dev)
-        efmax = int(wl.ef.max())
         ctx = uhnsw.Context(0)
         ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_F16)
+        # recall reachable through EFMAX (ef_i = max(k_i, E)), FP16 walk, FP32 re-rank
+        sweep = sweep_ef(ctx, dict(fused=1), "fp16 sweep")
+        ok = [r for r in sweep if r["recall_at_10"] >= TARGET_RECALL]
+        pick = ok[0] if ok else max(sweep, key=lambda r: r["recall_at_10"])
+        out["ef_sweep"] = sweep
+        # the batching form at the chosen E: autotuned, one persistent launch, hipGraph
+        ef_np = np.maximum(wl.k, pick["E"]).astype(np.int32)
+        ef_t = torch.from_numpy(ef_np).to(dev)
+        efmax = int(ef_np.max())
         prm = ctx.autotune(q, p, k, ef_t, kmax, efmax, params=uhnsw.default_params(fused=1, persistent=1),
                            allow_beam=True)
         prm.graph = 1
         dt = timed_run(ctx, ef_t, efmax, prm, a.steps)
         rec, err = quality(ids.cpu().numpy(), dists.cpu().numpy())
-        out["forms"]["fp16-batched"] = dict(qps=round(wl.nq / dt, 1), ms_per_launch=round(dt * 1e3, 3),
+        out["forms"]["fp16-batched"] = dict(E=pick["E"], qps=round(wl.nq / dt, 1), ms_per_launch=round(dt * 1e3, 3),
                                             recall_at_10=round(rec, 4), max_rel_dist_err=err,
                                             beam=prm.beam_width, slots=prm.visited_slots,
                                             wpb=prm.waves_per_block, persistent=prm.persistent)
         log("fp16-batched", json.dumps(out["forms"]["fp16-batched"]))
         ctx.close()
-        out["serving"] = serving(torch, uhnsw, wl, g1, g2, gt, efmax, storage=uhnsw.STORE_F16, k_max=kmax,
-                                 label="FP16")
+        # serving: at the configuration's own ef (max(k, 128)) and at the chosen E
+        out["serving"] = []
+        for E in sorted({128, pick["E"]}):
+            out["serving"].append(serving(torch, uhnsw, wl, g1, g2, gt, max(E, kmax), storage=uhnsw.STORE_F16,
+                                          k_max=kmax, label=f"FP16 (E={E})",
+                                          params=uhnsw.default_params(beam_width=1)))
     elif a.workload == 4:
+        ctx = uhnsw.Context(0)
+        ctx.load_graphs(wl.base, g1, g2)
+        out["ef_sweep"] = sweep_ef(ctx, {}, "sweep (ef_i = max(k_i, E))")
+        ctx.close()
         ef_t = torch.from_numpy(wl.ef).to(dev)
         efmax = int(wl.ef.max())
         for name, batched, pipe in (("plain", False, 1), ("batched", True, 1), ("batched-2-streams", True, 2)):
@@ -447,7 +506,7 @@ def run_secondary(a, torch, uhnsw, sg, synth):
             ctx = uhnsw.Context(0)
             ctx.load_graphs(wl.base, g1, g2, storage=storage)
             sweep = []
-            for ef in EF_GRID:
+            for ef in EF_SWEEP:
                 ef_t = torch.full((wl.nq,), ef, dtype=torch.int32, device=dev)
                 prm = uhnsw.default_params(fused=1)
                 dt = timed_run(ctx, ef_t, ef, prm, a.steps)
@@ -602,11 +661,13 @@ def main():
                     help="skip the host-pointer (PCIe-inclusive) leg of the FP32 form")
     ap.add_argument("--workload", type=int, default=2, choices=(2, 3, 4, 5, 7),
                     help="2: the headline workload; 3: precision form; 4: batching form; "
-                         "5: serving form (n = 1,000,000 of its 10,000,000); 7: the headline vectors on "
+                         "5: serving form (10,000,000 x 96, graphs built on the GPU); 7: the headline vectors on "
                          "the extended index (G_0.5 + G_1, p over 0.2..1.0)")
     ap.add_argument("--sweep", action="store_true",
                     help="method diagnostics on the headline workload instead of the benchmark: the "
                          "verification ablation, the t / tau study and per-graph recall across p")
+    ap.add_argument("--reduced", action="store_true",
+                    help="--workload 5 at 1,000,000 of its 10,000,000 rows (CPU-built graphs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()

@@ -384,7 +384,9 @@ void uhnsw_built_graph_free(uhnsw_built_graph *g);
  * one fused walk+verify launch on the first idle stream, so batches that
  * arrive while others run overlap on the device. Admission: at most
  * max_inflight queries at once (default: the device's resident-wave
- * capacity, one wave per query, 16 per CU) and per-stream device buffers
+ * capacity for the fused kernel, one wave per query: CUs times the waves
+ * per CU its LDS plan for k_max, ef_max and the visited-cache size and its
+ * registers allow, from the occupancy query) and per-stream device buffers
  * within hbm_budget. A query's result is the same whichever batch carries
  * it. While a server runs, the context must not be used for other searches
  * and must not be destroyed. */
@@ -433,16 +435,24 @@ int uhnsw_serve_poll(uhnsw_server *srv, uhnsw_serve_result *out, int32_t max, in
 
 /* Counters: info[0] slots, [1] free slots, [2] pending, [3] batches
  * launched, [4] queries completed, [5] most batches in flight at once,
- * [6] batch size limit, [7] streams. */
+ * [6] batch size limit, [7] streams, [8] resident waves per CU of the
+ * fused kernel under the LDS plan, [9] CUs. info has 10 entries. */
 int uhnsw_serve_info(uhnsw_server *srv, int64_t *info);
 
 /* Drive the server with a fixed arrival schedule (arrival_us[i] = offset of
- * query i from the call, ascending): submit each at its time (waiting for
- * slots when busy), collect every result into results[i]. Times in the
- * results are in the caller's clock, submit_us = the scheduled arrival, so
- * done_us - submit_us includes queueing. Synchronous. */
-int uhnsw_serve_drive(uhnsw_server *srv, int64_t n, const float *queries, const float *p, const int32_t *k,
-                      const int32_t *ef, const double *arrival_us, uhnsw_serve_result *results);
+ * arrival i from the call, ascending): submit each at its time (waiting for
+ * slots when busy) and collect every result. Arrival i carries the query
+ * vector queries[qidx[i]] (qidx may be NULL: queries[i]; the caller promises
+ * qidx[i] indexes a row of queries) with p[i], k[i], ef[i]. ids / dists [n x out_k]
+ * receive the first out_k entries of query i's row (-1 / +inf padded),
+ * stats [n] its counters (may be NULL), times [n x 3] its scheduled arrival,
+ * launch and completion in microseconds of the caller's clock (so
+ * completion - arrival includes queueing), status [n] its status.
+ * Synchronous. Errors: EINVAL (NULL array, out_k outside [1, KMAX]), or a
+ * query's submit error. */
+int uhnsw_serve_drive(uhnsw_server *srv, int64_t n, const float *queries, const int32_t *qidx, const float *p,
+                      const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
+                      float *dists, uhnsw_stats *stats, double *times, int32_t *status);
 
 /* Finish in-flight work, stop the dispatcher, free the server. */
 int uhnsw_serve_stop(uhnsw_server *srv);

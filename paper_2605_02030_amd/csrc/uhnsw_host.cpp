@@ -520,6 +520,29 @@ int check_result(const std::string &err, int r, char *msg, int32_t msg_len) {
 
 }  // namespace
 
+namespace uhnsw {
+// Waves of the fused kernel that stay resident per CU for this index and
+// these limits: its LDS plan (the list W, the visited cache, merge and
+// verification scratch per wave) and registers, as the occupancy query
+// reports them.
+int ctx_resident_waves(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params *prm_in, int *waves_per_cu) {
+    if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
+    uhnsw_params prm = *prm_in;
+    prm.fused = 1;
+    int r = check_params(c, prm);
+    if (r) return r;
+    Plan pl;
+    if ((r = make_plan(c, k_max, ef_max, prm, &pl))) return r;
+    const void *kp = search_kernel_ptr(c->layout, c->storage, prm.beam_width, c->variant == UHNSW_VARIANT_EXT);
+    int blocks = 0;
+    HIP_OR_FAIL(c, hipSetDevice(c->device));
+    HIP_OR_FAIL(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kp, pl.wpb * kWave,
+                                                                 (size_t)pl.search_bytes * pl.wpb));
+    *waves_per_cu = blocks * pl.wpb;
+    return UHNSW_OK;
+}
+}  // namespace uhnsw
+
 // ================================================================ C ABI
 extern "C" {
 

@@ -138,5 +138,7 @@ void ctx_servers(uhnsw_ctx *c, int delta);  // servers running on the context
 bool p_in_range(int variant, float p);  // the index variant's p range
 int ctx_device(const uhnsw_ctx *c);
 void ctx_set_error(uhnsw_ctx *c, const char *msg);  // the message uhnsw_last_error returns
+// resident waves per CU of the fused kernel under this LDS plan (occupancy)
+int ctx_resident_waves(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params *prm, int *waves_per_cu);
 
 }  // namespace uhnsw

@@ -77,6 +77,7 @@ struct uhnsw_server {
     std::atomic<int> error{0};
     std::string err;
     int64_t launched_batches = 0, completed = 0, max_overlap = 0;
+    int waves_per_cu = 0, cus = 0;  // the fused kernel's residency under the LDS plan
 };
 
 namespace {
@@ -297,9 +298,23 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
     // context's own streams hold some of them; more lanes than free queues
     // serialise behind each other and measured slower.
     const int streams = cfg->streams ? cfg->streams : 2;
-    // LDS budget: a query occupies one wave; admit at most as many queries
-    // as the device holds resident waves (16 per CU unless told otherwise)
-    const int wave_capacity = cus * 16;
+    // LDS budget: a query occupies one wave of the fused kernel; admit at
+    // most as many queries as the device keeps resident under the launch's
+    // LDS plan (W, visited cache and scratch per wave, from k_max, ef_max and
+    // the cache size) and register use, as the occupancy query reports
+    int wpc = 0;
+    {
+        uhnsw_params prm = cfg->params;
+        prm.persistent = 0;
+        const int rc = uhnsw::ctx_resident_waves(ctx, cfg->k_max, cfg->ef_max, &prm, &wpc);
+        if (rc != UHNSW_OK) {
+            delete S;
+            return rc;
+        }
+    }
+    S->waves_per_cu = wpc;
+    S->cus = cus;
+    const int wave_capacity = std::max(1, cus * wpc);
     int slots = cfg->max_inflight ? cfg->max_inflight : wave_capacity;
     int B = cfg->max_batch ? cfg->max_batch : std::max(64, wave_capacity / streams);
     // HBM budget: the per-lane device buffers must fit; shrink the batch
@@ -377,6 +392,8 @@ int uhnsw_serve_info(uhnsw_server *S, int64_t *info) {
     info[5] = S->max_overlap;
     info[6] = S->max_batch;
     info[7] = (int64_t)S->lanes.size();
+    info[8] = S->waves_per_cu;
+    info[9] = S->cus;
     return UHNSW_OK;
 }
 
@@ -395,9 +412,12 @@ int uhnsw_serve_stop(uhnsw_server *S) {
     return rc;
 }
 
-int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const float *p, const int32_t *k,
-                      const int32_t *ef, const double *arrival_us, uhnsw_serve_result *results) {
-    if (!S || n < 0 || (n > 0 && (!queries || !p || !k || !ef || !arrival_us || !results))) return UHNSW_EINVAL;
+int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const int32_t *qidx, const float *p,
+                      const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
+                      float *dists, uhnsw_stats *stats, double *times, int32_t *status) {
+    if (!S || n < 0 || out_k < 1 || out_k > UHNSW_KMAX ||
+        (n > 0 && (!queries || !p || !k || !ef || !arrival_us || !ids || !dists || !times || !status)))
+        return UHNSW_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
     const double off = now_us(S->t0);  // server clock at the driver's time zero
     int64_t next = 0, got = 0;
@@ -405,7 +425,8 @@ int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const fl
     while (got < n) {
         const double t = now_us(t0);
         while (next < n && arrival_us[next] <= t) {
-            const int rc = uhnsw_serve_submit(S, queries + (size_t)next * S->d, p[next], k[next], ef[next],
+            const int64_t row = qidx ? qidx[next] : next;
+            const int rc = uhnsw_serve_submit(S, queries + (size_t)row * S->d, p[next], k[next], ef[next],
                                               (uint64_t)next);
             if (rc == UHNSW_EBUSY) break;  // wait for a slot; the arrival time still counts
             if (rc != UHNSW_OK) return rc;
@@ -415,12 +436,16 @@ int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const fl
         const int rc = uhnsw_serve_poll(S, buf.data(), (int32_t)buf.size(), &m);
         if (rc != UHNSW_OK) return rc;
         for (int i = 0; i < m; ++i) {
-            const int64_t id = (int64_t)buf[i].tag;
-            results[id] = buf[i];
+            const uhnsw_serve_result &r = buf[i];
+            const int64_t id = (int64_t)r.tag;
+            std::memcpy(ids + id * out_k, r.ids, sizeof(int64_t) * out_k);
+            std::memcpy(dists + id * out_k, r.dists, sizeof(float) * out_k);
+            if (stats) stats[id] = r.stats;
             // times in the driver's clock; latency counts from the scheduled arrival
-            results[id].submit_us = arrival_us[id];
-            results[id].launch_us = buf[i].launch_us - off;
-            results[id].done_us = buf[i].done_us - off;
+            times[3 * id] = arrival_us[id];
+            times[3 * id + 1] = r.launch_us - off;
+            times[3 * id + 2] = r.done_us - off;
+            status[id] = r.status;
             ++got;
         }
         if (m == 0) std::this_thread::yield();

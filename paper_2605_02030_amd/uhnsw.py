@@ -107,7 +107,8 @@ uhnsw_serve_start = _sig("uhnsw_serve_start", ctypes.c_int, [_P, _P, ctypes.POIN
 uhnsw_serve_submit = _sig("uhnsw_serve_submit", ctypes.c_int, [_P, _P, ctypes.c_float, _I32, _I32, ctypes.c_uint64])
 uhnsw_serve_poll = _sig("uhnsw_serve_poll", ctypes.c_int, [_P, _P, _I32, ctypes.POINTER(_I32)])
 uhnsw_serve_info = _sig("uhnsw_serve_info", ctypes.c_int, [_P, _P])
-uhnsw_serve_drive = _sig("uhnsw_serve_drive", ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P])
+uhnsw_serve_drive = _sig("uhnsw_serve_drive", ctypes.c_int,
+                         [_P, _I64, _P, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P])
 uhnsw_serve_stop = _sig("uhnsw_serve_stop", ctypes.c_int, [_P])
 uhnsw_device_info = _sig("uhnsw_device_info", ctypes.c_int, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 uhnsw_last_timing = _sig("uhnsw_last_timing", ctypes.c_int,
@@ -451,37 +452,39 @@ class Server:
         return [buf[i] for i in range(n.value)]
 
     def info(self):
-        a = np.zeros(8, np.int64)
+        a = np.zeros(10, np.int64)
         uhnsw_serve_info(self.h, a.ctypes.data)
         return dict(zip(("slots", "free", "pending", "batches", "completed", "max_overlap", "max_batch",
-                         "streams"), a.tolist()))
+                         "streams", "waves_per_cu", "cus"), a.tolist()))
 
-    def drive(self, queries, p, k, ef, arrival_us, with_stats=False):
+    def drive(self, queries, p, k, ef, arrival_us, with_stats=False, out_k=None, qidx=None):
         """Submit on the given schedule, return (ids, dists, status, submit_us, launch_us, done_us)
-        (and the per-query stats as a STATS_DTYPE array when with_stats)."""
+        (and the per-query stats as a STATS_DTYPE array when with_stats); ids /
+        dists hold the first out_k (default: the server's k_max) entries of each
+        row. With qidx, arrival i carries queries[qidx[i]] (p, k, ef, arrival_us
+        are per arrival)."""
         queries = np.ascontiguousarray(queries, np.float32)
-        n = queries.shape[0]
+        n = queries.shape[0] if qidx is None else len(qidx)
+        if qidx is not None:
+            qidx = np.ascontiguousarray(qidx, np.int32)
+            assert qidx.min() >= 0 and qidx.max() < queries.shape[0]
         p = np.ascontiguousarray(p, np.float32)
         k = np.ascontiguousarray(k, np.int32)
         ef = np.ascontiguousarray(ef, np.int32)
         arr = np.ascontiguousarray(arrival_us, np.float64)
-        res = (uhnsw_serve_result * n)()
-        rc = uhnsw_serve_drive(self.h, n, queries.ctypes.data, p.ctypes.data, k.ctypes.data, ef.ctypes.data,
-                               arr.ctypes.data, res)
+        ok = int(out_k or self.cfg.k_max)
+        ids = np.empty((n, ok), np.int64)
+        dists = np.empty((n, ok), np.float32)
+        st = np.zeros(n, STATS_DTYPE) if with_stats else None
+        times = np.empty((n, 3), np.float64)
+        status = np.empty(n, np.int32)
+        rc = uhnsw_serve_drive(self.h, n, queries.ctypes.data, qidx.ctypes.data if qidx is not None else None,
+                               p.ctypes.data, k.ctypes.data, ef.ctypes.data, arr.ctypes.data, ok, ids.ctypes.data, dists.ctypes.data,
+                               st.ctypes.data if with_stats else None, times.ctypes.data, status.ctypes.data)
         if rc != UHNSW_OK:
             raise UhnswError(rc, "uhnsw_serve_drive failed")
-        raw = np.frombuffer(res, dtype=np.uint8).reshape(n, ctypes.sizeof(uhnsw_serve_result))
-        off_ids = uhnsw_serve_result.ids.offset
-        off_d = uhnsw_serve_result.dists.offset
-        ids = raw[:, off_ids:off_ids + 8 * UHNSW_KMAX].copy().view(np.int64)
-        dists = raw[:, off_d:off_d + 4 * UHNSW_KMAX].copy().view(np.float32)
-        status = np.array([r.status for r in res], np.int32)
-        t = np.array([(r.submit_us, r.launch_us, r.done_us) for r in res], np.float64)
-        if not with_stats:
-            return ids, dists, status, t[:, 0], t[:, 1], t[:, 2]
-        off_st = uhnsw_serve_result.stats.offset
-        st = raw[:, off_st:off_st + STATS_DTYPE.itemsize].copy().view(STATS_DTYPE).reshape(n)
-        return ids, dists, status, t[:, 0], t[:, 1], t[:, 2], st
+        out = (ids, dists, status, times[:, 0], times[:, 1], times[:, 2])
+        return out + (st,) if with_stats else out
 
     def stop(self):
         if getattr(self, "h", None):

@@ -10,7 +10,8 @@ definition of the U-HNSW paper, Sec. 4.1.2) on the seeded inputs from
   workload 4 (unitgauss-1.18M-d100): every 30th query starting at 1 (the
       K = 10 queries; 334 of 10,000);
   workload 5 at n = 1,000,000 (unitgauss-1M-d96, the serving form's shape
-      at a tenth of its size): every 10th query (200 of 2,000);
+      at a tenth of its size), and with --full at its n = 10,000,000
+      (unitgauss-10M-d96): every 10th query (200 of 2,000);
   workload 7 (mixture-1M-d128-pext, the extended variant's p over 0.2..1.0):
       every 10th query (1,000 of 10,000; 10 is coprime to the 9-value grid).
 
@@ -106,12 +107,14 @@ def main():
     ap.add_argument("--workload", type=int, default=2, choices=sorted(SAMPLE))
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--ideal", action="store_true")
+    ap.add_argument("--full", action="store_true",
+                    help="workload 5 at its full n = 10,000,000 (gt_unitgauss-10M-d96.npz)")
     a = ap.parse_args()
     if a.sweep:
         return sweep(a)
     if a.ideal:
         return ideal(a)
-    wl = synth.make_workload(a.workload, n=SIZE.get(a.workload))
+    wl = synth.make_workload(a.workload, n=None if a.full else SIZE.get(a.workload))
     first, stride = SAMPLE[a.workload]
     qidx = np.arange(first, wl.nq, stride, dtype=np.int32)
     out = os.path.join(HERE, f"gt_{wl.name}.npz")

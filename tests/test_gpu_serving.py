@@ -118,6 +118,28 @@ def test_admission_busy_and_budget(torch_cuda, ctxs, wl1):
     assert e.value.code == uhnsw.UHNSW_EBUSY
 
 
+def test_admission_slots_follow_lds_plan(torch_cuda, ctxs):
+    """Default slots = CUs x the fused kernel's resident waves per CU under
+    the launch's LDS plan: a larger visited cache or list (more LDS per wave)
+    admits fewer queries at once, never more."""
+    from paper_2605_02030_amd import uhnsw
+
+    waves = {}
+    for slots, ef_max in ((1024, 128), (4096, 128), (8192, 128), (1024, 2048)):
+        srv = uhnsw.Server(ctxs, k_max=100, ef_max=ef_max, params=uhnsw.default_params(visited_slots=slots))
+        try:
+            info = srv.info()
+        finally:
+            srv.stop()
+        _say(f"visited slots {slots}, ef_max {ef_max}: {info['waves_per_cu']} waves per CU, "
+             f"{info['slots']} query slots")
+        assert info["slots"] == info["waves_per_cu"] * info["cus"]
+        assert 1 <= info["waves_per_cu"] <= 32
+        waves[(slots, ef_max)] = info["waves_per_cu"]
+    assert waves[(1024, 128)] >= waves[(4096, 128)] >= waves[(8192, 128)]
+    assert waves[(1024, 128)] > waves[(1024, 2048)]  # ef 2048: a 16 KiB list per wave
+
+
 def test_reload_refused_while_serving(torch_cuda, wl1):
     """The server's thread searches on the context: replacing the index under
     it is refused until the server stops."""
