@@ -19,8 +19,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "_oracle.so")
 
 F32, BF16, F16 = 0, 1, 2
-L1, L2, L05 = 1, 2, 3  # base metrics of the walk (L05: sum sqrt|x - q|)
-VARIANT_STD, VARIANT_EXT = 0, 1
+L1, L2, L05, LP = 1, 2, 3, 4  # base metrics of the walk (L05: sum sqrt|x - q|; LP: sum |x - q|^mp)
+VARIANT_STD, VARIANT_EXT, VARIANT_PGRAPH = 0, 1, 2
 MAXL = 32
 _lib = None
 
@@ -50,7 +50,8 @@ class OrcData(ctypes.Structure):
 class OrcParams(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("cutoff", ctypes.c_float), ("t_param", ctypes.c_int),
                 ("kappa", ctypes.c_int), ("w", ctypes.c_int), ("early_abort", ctypes.c_int),
-                ("g", ctypes.c_int), ("v", ctypes.c_int), ("cache_slots", ctypes.c_int), ("variant", ctypes.c_int)]
+                ("g", ctypes.c_int), ("v", ctypes.c_int), ("cache_slots", ctypes.c_int), ("variant", ctypes.c_int),
+                ("walk_p", ctypes.c_double)]
 
 
 class OrcStats(ctypes.Structure):
@@ -82,12 +83,13 @@ def _load():
         L.orc_f16_to_f32.restype = ctypes.c_float
         L.orc_f16_to_f32.argtypes = [ctypes.c_uint16]
         L.orc_base_dist.restype = ctypes.c_float
-        L.orc_base_dist.argtypes = [_P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_base_dist.argtypes = [_P, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int]
         L.orc_m_of.restype = ctypes.c_int
         L.orc_m_of.argtypes = [ctypes.c_double, ctypes.c_int]
         L.orc_knn_search.restype = ctypes.c_int
-        L.orc_knn_search.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P]
+        L.orc_knn_search.argtypes = [_P, _P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P, _P]
         L.orc_verify.restype = ctypes.c_int
         L.orc_verify.argtypes = [_P, _P, ctypes.c_float, ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, _P, _P, _P, _P]
@@ -144,10 +146,11 @@ def widen(h, storage):
     return np.array([f(int(v)) for v in flat], np.float32).reshape(np.shape(h))
 
 
-def base_dist(x, q, metric, g, v, storage=F32) -> float:
+def base_dist(x, q, metric, g, v, storage=F32, mp=0.0) -> float:
+    """The walk's FP32 key of row x for query q (mp: the p of metric LP)."""
     x = np.ascontiguousarray(x) if storage != F32 else _f32(x)
     q = _f32(q)
-    return _load().orc_base_dist(_ptr(x), storage, _ptr(q), q.shape[0], metric, g, v)
+    return _load().orc_base_dist(_ptr(x), storage, _ptr(q), q.shape[0], metric, float(mp), g, v)
 
 
 def m_of(tau, K) -> int:
@@ -220,19 +223,20 @@ class Params:
     v: int = 4
     cache_slots: int = 0
     variant: int = VARIANT_STD  # VARIANT_EXT: g1 = G_0.5 (L0.5), g2 = G_1 (L1), cutoff 0.6 (Sec. 4.5)
+    walk_p: float = 0.0  # VARIANT_PGRAPH: g1 = G_p walked under L_walk_p (Sec. 4.3's per-p HNSW)
 
     def c(self) -> OrcParams:
         return OrcParams(self.tau, self.cutoff, self.t_param, self.kappa, self.w, self.early_abort,
-                         self.g, self.v, self.cache_slots, self.variant)
+                         self.g, self.v, self.cache_slots, self.variant, self.walk_p)
 
 
-def knn_search(G: Graph, D: Data, q, metric, ef, t, w=1, g=8, v=4, cache_slots=0):
-    """C (ids, base keys) and stats of KnnSearch for one query."""
+def knn_search(G: Graph, D: Data, q, metric, ef, t, w=1, g=8, v=4, cache_slots=0, mp=0.0):
+    """C (ids, base keys) and stats of KnnSearch for one query (mp: the p of metric LP)."""
     q = _f32(q)
     ids = np.empty(max(t, 1), np.int32)
     keys = np.empty(max(t, 1), np.float32)
     st = OrcStats()
-    nc = _load().orc_knn_search(G.ref, D.ref, _ptr(q), metric, ef, t, w, g, v, cache_slots,
+    nc = _load().orc_knn_search(G.ref, D.ref, _ptr(q), metric, float(mp), ef, t, w, g, v, cache_slots,
                                 _ptr(ids), _ptr(keys), ctypes.byref(st))
     return ids[:nc], keys[:nc], st
 

@@ -137,7 +137,10 @@ static float elem(const void *x, int storage, int64_t j) {
  * Sec. 4.5's extended pair: G_0.5 under L0.5, G_1 under L1).
  * delta_1 = sum |x_j - q_j|, delta_2 = sum (x_j - q_j)^2 (squared L2, rank-
  * equivalent to L2), delta_0.5 = sum sqrt|x_j - q_j| (the L0.5 distance is
- * its square, so the two rank alike). Computed in FP32 (the paper's kernels
+ * its square, so the two rank alike), and for a graph built for one p
+ * (Sec. 4.3's per-p HNSW) delta_p = sum |x_j - q_j|^p (the L_p distance to
+ * the power p; each term taken in FP64 and rounded once to FP32). Computed
+ * in FP32 (the paper's kernels
  * are single precision, Sec. 2.1) in one fixed order, so that any
  * implementation that follows the same order gets the same bits:
  *   element j belongs to lane (j / v) mod g; each lane sums its elements in
@@ -145,7 +148,7 @@ static float elem(const void *x, int storage, int64_t j) {
  *   correctly rounded FP32 square root); lanes then combine pairwise, lane
  *   l < o taking s_l + s_{l+o}, for o = g/2, g/4, ..., 1.
  */
-float orc_base_dist(const void *x, int storage, const float *q, int d, int metric, int g, int v) {
+float orc_base_dist(const void *x, int storage, const float *q, int d, int metric, double mp, int g, int v) {
     float s[64];
     for (int l = 0; l < g; l++) s[l] = 0.0f;
     for (int j = 0; j < d; j++) {
@@ -155,6 +158,8 @@ float orc_base_dist(const void *x, int storage, const float *q, int d, int metri
             s[lane] = s[lane] + fabsf(diff);
         else if (metric == ORC_L05)
             s[lane] = s[lane] + sqrtf(fabsf(diff));
+        else if (metric == ORC_LP) /* |diff|^p in FP64, rounded once to FP32 */
+            s[lane] = s[lane] + (float)pow((double)fabsf(diff), mp);
         else
             s[lane] = fmaf(diff, diff, s[lane]);
     }
@@ -163,10 +168,10 @@ float orc_base_dist(const void *x, int storage, const float *q, int d, int metri
     return s[0];
 }
 
-static float base_key(const orc_data *D, int32_t id, const float *q, int metric, int g, int v) {
+static float base_key(const orc_data *D, int32_t id, const float *q, int metric, double mp, int g, int v) {
     size_t es = D->walk_storage == ORC_F32 ? 4 : 2;
     const char *row = (const char *)D->walk_base + (size_t)id * (size_t)D->d * es;
-    return orc_base_dist(row, D->walk_storage, q, D->d, metric, g, v);
+    return orc_base_dist(row, D->walk_storage, q, D->d, metric, mp, g, v);
 }
 
 /* ====================================================== KnnSearch
@@ -220,12 +225,12 @@ static uint32_t cache_slot(int32_t id, int slots) {
     return (uint32_t)(h >> 40) & (uint32_t)(slots - 1);
 }
 
-int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int metric, int ef, int t, int w, int g,
-                   int v, int cache_slots, int32_t *c_ids, float *c_keys, orc_stats *st) {
+int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int metric, double mp, int ef, int t, int w,
+                   int g, int v, int cache_slots, int32_t *c_ids, float *c_keys, orc_stats *st) {
     int n_b = 0, n_exp = 0;
     /* descent over the upper layers */
     int32_t cur = G->entry;
-    float kcur = base_key(D, cur, q, metric, g, v);
+    float kcur = base_key(D, cur, q, metric, mp, g, v);
     n_b++;
     for (int l = G->max_level; l >= 1; l--) {
         for (;;) {
@@ -234,7 +239,7 @@ int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int me
             float kbest = 0.0f;
             for (int64_t e = G->row_ptr[l][r]; e < G->row_ptr[l][r + 1]; e++) {
                 int32_t u = G->col[l][e];
-                float ku = base_key(D, u, q, metric, g, v);
+                float ku = base_key(D, u, q, metric, mp, g, v);
                 n_b++;
                 if (best < 0 || ku < kbest || (ku == kbest && u < best)) {
                     best = u;
@@ -305,7 +310,7 @@ int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int me
             nU = keep;
         }
         for (int i = 0; i < nU; i++) {
-            W[nW].key = base_key(D, U[i], q, metric, g, v);
+            W[nW].key = base_key(D, U[i], q, metric, mp, g, v);
             W[nW].id = U[i];
             W[nW].expanded = 0;
             nW++;
@@ -431,7 +436,9 @@ int orc_verify(const orc_data *D, const float *q, float p, int K, const int32_t 
  * K = 50), kappa = max(K, 2) (kappa = K by default and kappa > 1),
  * tau = 0.92. The extended variant (Sec. 4.5) runs the same steps with
  * G_0.5 in G1's place and G_1 in G2's, and a cutoff of 0.6 (the caller's
- * prm->cutoff).
+ * prm->cutoff). The per-p variant runs them on a graph built for one p
+ * (Sec. 4.3's HNSW baseline): its walk ranks by that p's sum, so for a
+ * query of the same p the verification only confirms C's first K.
  */
 int orc_query(const orc_graph *g1, const orc_graph *g2, const orc_data *D, const float *q, float p, int K, int ef,
               const orc_params *prm, int32_t *ids, double *S, double *dist, int32_t *c_ids, float *c_keys,
@@ -448,9 +455,11 @@ int orc_query(const orc_graph *g1, const orc_graph *g2, const orc_data *D, const
     int m = orc_m_of(prm->tau, K);
     int32_t *ci = c_ids ? c_ids : (int32_t *)malloc(sizeof(int32_t) * (size_t)t);
     float *ck = c_keys ? c_keys : (float *)malloc(sizeof(float) * (size_t)t);
-    int metric = prm->variant == ORC_VARIANT_EXT ? (use_g1 ? ORC_L05 : ORC_L1) : (use_g1 ? ORC_L1 : ORC_L2);
-    int nc = orc_knn_search(use_g1 ? g1 : g2, D, q, metric, ef, t, prm->w, prm->g, prm->v, prm->cache_slots, ci, ck,
-                            st);
+    int metric = prm->variant == ORC_VARIANT_EXT      ? (use_g1 ? ORC_L05 : ORC_L1)
+                 : prm->variant == ORC_VARIANT_PGRAPH ? (use_g1 ? ORC_LP : ORC_L2)
+                                                      : (use_g1 ? ORC_L1 : ORC_L2);
+    int nc = orc_knn_search(use_g1 ? g1 : g2, D, q, metric, prm->walk_p, ef, t, prm->w, prm->g, prm->v,
+                            prm->cache_slots, ci, ck, st);
     int nr = orc_verify(D, q, p, K, ci, nc, kappa, m, prm->early_abort, ids, S, dist, st);
     if (!c_ids) free(ci);
     if (!c_keys) free(ck);

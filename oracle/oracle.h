@@ -14,7 +14,10 @@
  *   orc_bruteforce .................. pinned (library cdist top-K)
  *   orc_base_dist ................... pinned (exact on integer data, and for
  *                                      L0.5 on perfect-square differences;
- *                                      FP64 error bound; lane-order cases)
+ *                                      FP64 error bound; lane-order cases;
+ *                                      L_p: p = 1 is L1 bit for bit, p = 0.5
+ *                                      on perfect squares is L0.5, any p on
+ *                                      differences in {0, 1} counts them)
  *   orc_to_bf16 / orc_to_f16 ........ pinned (numpy float16, torch bfloat16)
  *   orc_knn_search .................. pinned (ef = n on a connected graph is
  *                                      the exact base-metric top-t; lossy
@@ -33,15 +36,21 @@
 #define ORC_BF16 1
 #define ORC_F16 2
 
-/* base metrics of the walk: L1, squared L2, and L0.5 as sum sqrt|x - q| */
+/* base metrics of the walk: L1, squared L2, L0.5 as sum sqrt|x - q|, and
+ * L_p for a fixed p (the metric parameter mp) as sum |x - q|^p, the walk of
+ * an HNSW graph built for that p (the per-p HNSW of Sec. 4.3) */
 #define ORC_L1 1
 #define ORC_L2 2
 #define ORC_L05 3
+#define ORC_LP 4
 
 /* index variants: the paper's default pair (G1 under L1, G2 under L2) and
  * the extended pair of Sec. 4.5 (G_0.5 under L0.5, G_1 under L1) */
 #define ORC_VARIANT_STD 0
 #define ORC_VARIANT_EXT 1
+/* a graph built for one p (walk_p): g1 = G_p walked under L_p, g2 walked
+ * under L2 (taken only when p > cutoff) */
+#define ORC_VARIANT_PGRAPH 2
 
 typedef struct {
     int64_t n;
@@ -72,7 +81,8 @@ typedef struct {
     int g, v;        /* lane-group size and elements per lane-load of the base distance */
     int cache_slots; /* 0 = exact visited set; else lossy cache of this many slots (power of 2) */
     int variant;     /* ORC_VARIANT_STD: g1 = G1 (L1), g2 = G2 (L2); ORC_VARIANT_EXT: g1 = G_0.5
-                        (L0.5), g2 = G_1 (L1) */
+                        (L0.5), g2 = G_1 (L1); ORC_VARIANT_PGRAPH: g1 = G_p (L_walk_p), g2 (L2) */
+    double walk_p;   /* ORC_VARIANT_PGRAPH: the p G_p was built for */
 } orc_params;
 
 typedef struct {
@@ -98,12 +108,12 @@ float orc_bf16_to_f32(uint16_t h);
 float orc_f16_to_f32(uint16_t h);
 void orc_convert(const float *src, int64_t cnt, int storage, uint16_t *dst);
 
-float orc_base_dist(const void *x, int storage, const float *q, int d, int metric, int g, int v);
+float orc_base_dist(const void *x, int storage, const float *q, int d, int metric, double mp, int g, int v);
 
 int orc_m_of(double tau, int K);
 
-int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int metric, int ef, int t, int w, int g,
-                   int v, int cache_slots, int32_t *c_ids, float *c_keys, orc_stats *st);
+int orc_knn_search(const orc_graph *G, const orc_data *D, const float *q, int metric, double mp, int ef, int t, int w,
+                   int g, int v, int cache_slots, int32_t *c_ids, float *c_keys, orc_stats *st);
 
 int orc_verify(const orc_data *D, const float *q, float p, int K, const int32_t *C, int nC, int kappa, int m,
                int early_abort, int32_t *ids, double *S, double *dist, orc_stats *st);
