@@ -80,6 +80,14 @@ typedef struct {
 #define UHNSW_VARIANT_EXT 1    /* G_0.5 under L0.5 (walk key sum sqrt|x - q|),
                                   G_1 under L1; p in [0.2, 1]; cutoff 0.6
                                   (Sec. 4.5)                                   */
+#define UHNSW_VARIANT_PGRAPH 2 /* the per-p HNSW baseline (Sec. 4.3, Fig. 4):
+                                  graphs[0] = G_p built for graph_p, walked
+                                  under sum |x - q|^graph_p (v_log / v_exp);
+                                  graphs[1] under L2 (only for p above the
+                                  cutoff); p in [0.2, 2]; cutoff +inf: every
+                                  query walks G_p and is verified under its
+                                  own p (a query of p = graph_p is HNSW on
+                                  its own metric)                             */
 
 /* The resident index: base vectors (host, n x d FP32 row-major) and the two
  * base graphs, graphs[0] = G1 (built under L1), graphs[1] = G2 (under L2);
@@ -91,6 +99,8 @@ typedef struct {
     int32_t storage;          /* UHNSW_STORE_* for the walk                   */
     uhnsw_graph graphs[2];
     int32_t variant;          /* UHNSW_VARIANT_*; 0 (zero-initialised) = STD  */
+    float graph_p;            /* UHNSW_VARIANT_PGRAPH: the p graphs[0] was
+                                 built for, in [0.2, 2]; ignored otherwise   */
 } uhnsw_index;
 
 /* Algorithm 1's parameters (Sec. 3.1) and execution knobs. */
@@ -189,7 +199,8 @@ int uhnsw_reset(uhnsw_ctx *ctx);
  * 2M / M, neighbour not on the layer, a row listing one neighbour twice or
  * the node itself (a neighbour list is a set of other nodes, Sec. 2.2),
  * entry point not on the top layer, d > UHNSW_DMAX, M0 > 64, a non-finite
- * base value, an unknown variant),
+ * base value, an unknown variant, graph_p outside [0.2, 2] for
+ * UHNSW_VARIANT_PGRAPH),
  * ESTATE (a server is running on the context), ENOMEM, EDEVICE. */
 int uhnsw_load_graphs(uhnsw_ctx *ctx, const uhnsw_index *idx);
 
@@ -227,7 +238,8 @@ int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const cha
  *   row, min(k[i], |C_i|) results ascending by (L_p distance, id); the rest
  *   of the row is id -1, dist +inf. stats [nq] may be NULL.
  * Errors: EINVAL (NULL pointer, nq < 0, p not finite or outside the
- * index's range ([0.5, 2]; [0.2, 1] for UHNSW_VARIANT_EXT),
+ * index's range ([0.5, 2]; [0.2, 1] for UHNSW_VARIANT_EXT; [0.2, 2] for
+ * UHNSW_VARIANT_PGRAPH),
  * k < 1 or > UHNSW_KMAX, ef < k or > UHNSW_EFMAX, k_stride < max k, a
  * non-finite query value),
  * ESTATE (no index), ENOMEM, EDEVICE. */
@@ -339,8 +351,10 @@ int uhnsw_last_timing_split(const uhnsw_ctx *ctx, float *prepass_ms, float *walk
 /* ------------------------------------------------- graph construction
  * GPU construction of one HNSW base graph (HNSW's layered graph, Sec. 2.2;
  * building G1 and G2 is the method's up-front cost, Sec. 4.4.3, Table 3)
- * under metric 1 (L1, for G1 and G_1), 2 (squared L2, for G2) or 3
- * (sum sqrt|x - q|, for G_0.5), on the context's device:
+ * under metric 1 (L1, for G1 and G_1), 2 (squared L2, for G2), 3
+ * (sum sqrt|x - q|, for G_0.5) or 4 (sum |x - q|^metric_p, for the per-p
+ * baseline's G_p; each term exp2(p log2|x - q|) on v_log / v_exp), on the
+ * context's device:
  *   - node levels floor(-ln(U_v) / ln M) with U_v in (0, 1] from
  *     splitmix64(seed ^ v * 0x9E3779B97F4A7C15) (top 53 bits + 1) / 2^53,
  *     capped at 30;
@@ -355,21 +369,24 @@ int uhnsw_last_timing_split(const uhnsw_ctx *ctx, float *prepass_ms, float *walk
  *   - distances in FP32 in one order: element j summed by lane (j / 4) mod
  *     16 of 16 lanes in ascending j (L2 by fused multiply-add), the lanes
  *     combined pairwise (o = 8, 4, 2, 1).
- * The result is deterministic and identical to the CPU input builder's
- * (same steps, same distance order) for the same arguments.
+ * The result is deterministic and, for metrics 1-3, identical to the CPU
+ * input builder's (same steps, same distance order) for the same arguments.
+ * metric_p is read for metric 4 only (in [0.2, 2]).
  * base: host, n x d FP32 row-major (copied; the context's loaded index is
  * not used or changed). *out receives a graph the caller frees with
  * uhnsw_built_graph_free.
- * Errors: EINVAL (NULL, n < 1, d outside [1, UHNSW_DMAX], metric, M outside
+ * Errors: EINVAL (NULL, n < 1, d outside [1, UHNSW_DMAX], metric or metric_p, M outside
  * [2, 31], ef_construction outside [1, UHNSW_EFMAX], batch_max outside
  * [1, 65536], a non-finite value), EUNSUPPORTED (upper layers above 2^31
  * ids), ENOMEM, EDEVICE; the message is uhnsw_last_error(ctx). */
 #define UHNSW_METRIC_L1 1
 #define UHNSW_METRIC_L2 2
 #define UHNSW_METRIC_L05 3
+#define UHNSW_METRIC_LP 4
 typedef struct uhnsw_built_graph uhnsw_built_graph;
-int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, int32_t M,
-                      int32_t ef_construction, uint64_t seed, int32_t batch_max, uhnsw_built_graph **out);
+int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, float metric_p,
+                      int32_t M, int32_t ef_construction, uint64_t seed, int32_t batch_max,
+                      uhnsw_built_graph **out);
 
 /* The built graph as a uhnsw_graph (per-layer CSR; pointers into *g, valid
  * until uhnsw_built_graph_free), ready for uhnsw_index.graphs[]; the build's

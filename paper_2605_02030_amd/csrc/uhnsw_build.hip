@@ -1,4 +1,4 @@
-// GPU construction of the HNSW base graphs G1, G2 (and G_0.5). Building the
+// GPU construction of the HNSW base graphs G1, G2 (and G_0.5, G_p). Building the
 // graphs is U-HNSW's up-front cost (Sec. 4.4.3, Table 3); the graph itself is
 // HNSW's layered proximity graph (Sec. 2.2). This builds the same graph as
 // the deterministic CPU input builder (synth/hnsw_build.c), edge for edge:
@@ -17,7 +17,8 @@
 //            it with the same heuristic);
 //   distance FP32 in one fixed order: element j summed by lane (j / 4) mod 16
 //            of 16 lanes in ascending j (L2 by fused multiply-add), the lanes
-//            combined pairwise.
+//            combined pairwise (metric 4, sum |x - q|^p for the per-p
+//            baseline, takes each term on v_log / v_exp and has no CPU twin).
 //
 // The layer search is the walk's sorted list with a bounded LDS visited
 // cache, which returns the same list as an exact visited set (a forgotten
@@ -49,6 +50,7 @@ struct BuildArgs {
     const int8_t *level; // [n]
     int32_t M, M0, efc;
     int32_t ef_cap, vis_bits, vis_kbits, lds_wave_bytes;
+    float metric_p;      // metric 4: the p of sum |x - q|^p
     // plan step
     int64_t done;
     int32_t b, lmax, ep;
@@ -105,7 +107,7 @@ __device__ __forceinline__ int32_t *layer_row(const BuildArgs &A, int32_t v, int
 template <int NCH, int MET>
 __device__ __forceinline__ void bdist(const BuildArgs &A, const int32_t *ids, int nrows, const float (&qv)[NCH][4],
                                       float *keys) {
-    rows_base_dist<kBG, NCH, float, MET, 32>(A.base, A.pitch, ids, nrows, qv, keys);
+    rows_base_dist<kBG, NCH, float, MET, 32>(A.base, A.pitch, ids, nrows, qv, keys, nullptr, A.metric_p);
 }
 
 // Best-first search of layer l from (ep, dep) with a list bounded by ef; the
@@ -329,15 +331,17 @@ hipError_t launch_link_met(const BuildArgs &a, int nch, hipStream_t s) {
 }
 
 hipError_t launch_plan(const BuildArgs &a, int metric, int nch, hipStream_t s) {
-    return metric == 1 ? launch_plan_met<kMetL1>(a, nch, s)
+    return metric == 1   ? launch_plan_met<kMetL1>(a, nch, s)
            : metric == 2 ? launch_plan_met<kMetL2>(a, nch, s)
-                         : launch_plan_met<kMetL05>(a, nch, s);
+           : metric == 3 ? launch_plan_met<kMetL05>(a, nch, s)
+                         : launch_plan_met<kMetLp>(a, nch, s);
 }
 
 hipError_t launch_link(const BuildArgs &a, int metric, int nch, hipStream_t s) {
-    return metric == 1 ? launch_link_met<kMetL1>(a, nch, s)
+    return metric == 1   ? launch_link_met<kMetL1>(a, nch, s)
            : metric == 2 ? launch_link_met<kMetL2>(a, nch, s)
-                         : launch_link_met<kMetL05>(a, nch, s);
+           : metric == 3 ? launch_link_met<kMetL05>(a, nch, s)
+                         : launch_link_met<kMetLp>(a, nch, s);
 }
 
 uint64_t splitmix64(uint64_t x) {
@@ -399,8 +403,9 @@ struct uhnsw_built_graph {
 
 extern "C" {
 
-int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, int32_t M,
-                      int32_t ef_construction, uint64_t seed, int32_t batch_max, uhnsw_built_graph **out) {
+int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, float metric_p,
+                      int32_t M, int32_t ef_construction, uint64_t seed, int32_t batch_max,
+                      uhnsw_built_graph **out) {
     if (!ctx) return UHNSW_EINVAL;
     auto build_fail = [ctx](int code, const std::string &msg) {
         ctx_set_error(ctx, ("uhnsw_build_graph: " + msg).c_str());
@@ -410,7 +415,10 @@ int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, i
     *out = nullptr;
     if (n < 1 || n > INT32_MAX) return build_fail(UHNSW_EINVAL, "n outside [1, 2^31)");
     if (d < 1 || d > UHNSW_DMAX) return build_fail(UHNSW_EINVAL, "d outside [1, UHNSW_DMAX]");
-    if (metric < 1 || metric > 3) return build_fail(UHNSW_EINVAL, "metric must be 1 (L1), 2 (L2) or 3 (L0.5)");
+    if (metric < 1 || metric > 4)
+        return build_fail(UHNSW_EINVAL, "metric must be 1 (L1), 2 (L2), 3 (L0.5) or 4 (L_p)");
+    if (metric == 4 && !(metric_p >= 0.2f && metric_p <= 2.0f))
+        return build_fail(UHNSW_EINVAL, "metric_p outside [0.2, 2]");
     if (M < 2 || 2 * M >= kWave) return build_fail(UHNSW_EINVAL, "M outside [2, 31]");
     if (ef_construction < 1 || ef_construction > UHNSW_EFMAX)
         return build_fail(UHNSW_EINVAL, "ef_construction outside [1, UHNSW_EFMAX]");
@@ -522,6 +530,7 @@ int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, i
     a.M = M;
     a.M0 = M0;
     a.efc = ef_construction;
+    a.metric_p = metric == 4 ? metric_p : 0.0f;
     a.ef_cap = ef_cap;
     a.vis_bits = vis_bits;
     a.vis_kbits = vis_kbits;

@@ -128,9 +128,13 @@ struct Elem<f16_t> {
 // host and the query checks guarantee it), rooted by sqrt_rn_large.
 // kMetL05T: the same key when every value is an integer in [0, 255] (so is
 // |x - q|): the roots come from a 256-entry table of sqrtf(i) in LDS.
-constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3, kMetL05F = 4, kMetL05T = 5;
-// how the L0.5 roots are taken for a query (see above)
-constexpr int kRootSqrtf = 0, kRootShort = 1, kRootTable = 2;
+// kMetLp: sum |x - q|^pw for a fixed pw (a graph built for one p, the
+// per-p HNSW of Sec. 4.3), each term exp2(pw log2|x - q|) on v_log_f32 /
+// v_exp_f32 as in the verification.
+constexpr int kMetL1 = 1, kMetL2 = 2, kMetL05 = 3, kMetL05F = 4, kMetL05T = 5, kMetLp = 6;
+// how the graph-0 key of an extended-kernel query is taken: the L0.5 roots
+// (see above), or kRootPow: the per-p variant's sum |x - q|^walk_p
+constexpr int kRootSqrtf = 0, kRootShort = 1, kRootTable = 2, kRootPow = 3;
 constexpr int kRootTableBytes = 256 * 4;
 // descent pre-pass LDS per wave: 64 ids + 64 keys (+ the root table)
 __host__ __device__ constexpr int descend_lds_wave_bytes(bool ext) { return 512 + (ext ? kRootTableBytes : 0); }
@@ -159,7 +163,7 @@ __device__ __forceinline__ float sqrt_rn_large(float x) {
 template <int G, int NCH, typename T, int MET, int RBV>
 __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64_t pitch,
                                                const int32_t *ids, int nrows, const float (&qv)[NCH][4],
-                                               float *keys, const float *sqt = nullptr) {
+                                               float *keys, const float *sqt = nullptr, float pw = 0.0f) {
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
     constexpr int RB = (RBV * 4 / (NCH * V * (int)sizeof(T))) > 0 ? (RBV * 4 / (NCH * V * (int)sizeof(T))) : 1;
@@ -198,6 +202,8 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
                         s = s + sqrt_rn_large(fabsf(dlt));
                     else if (MET == kMetL05T)
                         s = s + sqt[(int)fabsf(dlt)];
+                    else if (MET == kMetLp)
+                        s = s + __builtin_amdgcn_exp2f(pw * __builtin_amdgcn_logf(fabsf(dlt)));
                     else
                         s = s + sqrtf(fabsf(dlt));  // correctly rounded root
                 }
@@ -209,14 +215,21 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
     }
 }
 
-// lo: the query walks graph 0 (G1, or G_0.5 when EXT) rather than graph 1
-// (G2, or G_1 when EXT). root (EXT only): how the L0.5 roots are taken,
-// kRootTable reading sqt (LDS), kRootShort the short correctly rounded form.
+// lo: the query walks graph 0 (G1, or G_0.5 / G_p when EXT) rather than
+// graph 1 (G2, or G_1 / the L2 graph when EXT). root (EXT only): how the
+// graph-0 key is taken, kRootTable reading sqt (LDS), kRootShort the short
+// correctly rounded root, kRootPow the per-p variant's power pw (graph 1 is
+// then walked under L2).
 template <int G, int NCH, typename T, int RBV, bool EXT>
 __device__ __forceinline__ void base_dists(bool lo, int root, const float *sqt, const T *base, int64_t pitch,
                                            const int32_t *ids, int nrows, const float (&qv)[NCH][4],
-                                           float *keys) {
-    if (EXT && lo && root == kRootTable)
+                                           float *keys, float pw) {
+    if (EXT && root == kRootPow) {
+        if (lo)
+            rows_base_dist<G, NCH, T, kMetLp, RBV>(base, pitch, ids, nrows, qv, keys, nullptr, pw);
+        else
+            rows_base_dist<G, NCH, T, kMetL2, RBV>(base, pitch, ids, nrows, qv, keys);
+    } else if (EXT && lo && root == kRootTable)
         rows_base_dist<G, NCH, T, kMetL05T, RBV>(base, pitch, ids, nrows, qv, keys, sqt);
     else if (EXT && lo && root == kRootShort)
         rows_base_dist<G, NCH, T, kMetL05F, RBV>(base, pitch, ids, nrows, qv, keys);
@@ -458,7 +471,7 @@ __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kb
 // or NaN, K or ef outside their bounds.
 template <bool EXT>
 __device__ __forceinline__ bool query_bad(const SearchArgs &A, float p, int K, int ef) {
-    const bool p_ok = EXT ? (p >= 0.2f && p <= 1.0f) : (p >= 0.5f && p <= 2.0f);
+    const bool p_ok = p >= A.p_lo && p <= A.p_hi;
     return !p_ok || K < 1 || K > A.k_max || K > UHNSW_KMAX || ef < K || ef > A.ef_max || ef > A.ef_cap;
 }
 
@@ -471,6 +484,7 @@ __device__ __forceinline__ bool is_byte_value(float v) { return v >= 0.0f && v <
 // correctly rounded roots), else the short form when no difference can fall
 // below 2^-95, else sqrtf.
 __device__ __forceinline__ int l05_root_mode(const SearchArgs &A, bool no_tiny, bool bytes, float *sqt) {
+    if (A.walk_p > 0.0f) return kRootPow;  // the per-p variant
     if (A.l05_table && bytes) {
         for (int i = lane_id(); i < 256; i += kWave) sqt[i] = sqrtf((float)i);
         wave_sync();
@@ -485,12 +499,12 @@ __device__ __forceinline__ int l05_root_mode(const SearchArgs &A, bool no_tiny, 
 // Uid / Uk: 64-entry LDS scratch of the wave.
 template <int G, int NCH, typename T, int RBV, bool EXT>
 __device__ int32_t descend(const DevGraph &Gr, bool lo, int root, const float *sqt, const T *base, int64_t pitch,
-                           const float (&qv)[NCH][4], int32_t *Uid, float *Uk, float *kout, int *n_b) {
+                           const float (&qv)[NCH][4], int32_t *Uid, float *Uk, float *kout, int *n_b, float pw) {
     const int lane = lane_id();
     int32_t cur = Gr.entry;
     if (lane == 0) Uid[0] = cur;
     wave_sync();
-    base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, 1, qv, Uk);
+    base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, 1, qv, Uk, pw);
     wave_sync();
     float kcur = Uk[0];
     *n_b += 1;
@@ -502,7 +516,7 @@ __device__ int32_t descend(const DevGraph &Gr, bool lo, int root, const float *s
             const int cnt = popc64(ballot(nb >= 0));
             if (nb >= 0) Uid[lane] = nb;  // valid ids come first in each row
             wave_sync();
-            base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, cnt, qv, Uk);
+            base_dists<G, NCH, T, RBV, EXT>(lo, root, sqt, base, pitch, Uid, cnt, qv, Uk, pw);
             wave_sync();
             *n_b += cnt;
             float kb = lane < cnt ? Uk[lane] : INFINITY;
@@ -594,7 +608,8 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         kcur = A.ekey[qi];
         n_b = A.dnb[qi];
     } else {
-        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, root, L.sqt, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b);
+        cur = descend<G, NCH, T, RBV, EXT>(Gr, lo, root, L.sqt, base, pitch, qv, L.Uid, L.Uk, &kcur, &n_b,
+                                           A.walk_p);
     }
     const int32_t entry0 = cur;
     const int n_up = n_b;  // the descent's base distances
@@ -677,7 +692,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (nnew == 0) continue;
         if (fresh) L.Uid[lanes_below(fm)] = nb;
         wave_sync();
-        base_dists<G, NCH, T, RBV, EXT>(lo, root, L.sqt, base, pitch, L.Uid, nnew, qv, L.Uk);
+        base_dists<G, NCH, T, RBV, EXT>(lo, root, L.sqt, base, pitch, L.Uid, nnew, qv, L.Uk, A.walk_p);
         wave_sync();
         n_b += nnew;
         // With W full, a new entry not below W's last one cannot enter: keep
@@ -1064,7 +1079,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))
     const int root = EXT ? l05_root_mode(A, ballot(tiny) == 0, ballot(!byte) == 0, sqt) : kRootSqrtf;
     const int32_t cur = descend<G, NCH, T, 32, EXT>(A.g[gsel], lo, root, sqt,
                                                     reinterpret_cast<const T *>(A.walk_base), A.pitch, qv, Uid, Uk,
-                                                    &kcur, &n_b);
+                                                    &kcur, &n_b, A.walk_p);
     if (lane == 0) {
         O.entry[qi] = cur;
         O.ekey[qi] = kcur;

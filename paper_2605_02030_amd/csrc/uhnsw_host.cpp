@@ -77,6 +77,7 @@ struct uhnsw_ctx {
     int64_t n = 0;
     int32_t d = 0, storage = 0, layout = 0;
     int32_t variant = UHNSW_VARIANT_STD;
+    float graph_p = 0.0f;  // UHNSW_VARIANT_PGRAPH
     std::atomic<int> servers{0};  // uhnsw_serve_start .. uhnsw_serve_stop
     bool l05_fast = false;   // every base value 0 or of magnitude >= 2^-72
     bool l05_table = false;  // every base value an integer in [0, 255]
@@ -129,8 +130,15 @@ struct uhnsw_ctx {
 };
 
 namespace uhnsw {
+// the p range of an index variant
+void p_range(int variant, float *lo, float *hi) {
+    *lo = variant == UHNSW_VARIANT_STD ? 0.5f : 0.2f;
+    *hi = variant == UHNSW_VARIANT_EXT ? 1.0f : 2.0f;
+}
 bool p_in_range(int variant, float p) {
-    return variant == UHNSW_VARIANT_EXT ? (p >= 0.2f && p <= 1.0f) : (p >= 0.5f && p <= 2.0f);
+    float lo, hi;
+    p_range(variant, &lo, &hi);
+    return p >= lo && p <= hi;
 }
 int ctx_variant(const uhnsw_ctx *c) { return c->variant; }
 void ctx_servers(uhnsw_ctx *c, int delta) { c->servers += delta; }
@@ -470,8 +478,11 @@ int check_index(std::string *err, const uhnsw_index *idx) {
     if (idx->d < 1 || idx->d > UHNSW_DMAX) return fail(err, UHNSW_EINVAL, "d=%d outside [1, %d]", idx->d, UHNSW_DMAX);
     if (idx->storage < UHNSW_STORE_F32 || idx->storage > UHNSW_STORE_F16)
         return fail(err, UHNSW_EINVAL, "unknown storage %d", idx->storage);
-    if (idx->variant != UHNSW_VARIANT_STD && idx->variant != UHNSW_VARIANT_EXT)
+    if (idx->variant != UHNSW_VARIANT_STD && idx->variant != UHNSW_VARIANT_EXT &&
+        idx->variant != UHNSW_VARIANT_PGRAPH)
         return fail(err, UHNSW_EINVAL, "unknown variant %d", idx->variant);
+    if (idx->variant == UHNSW_VARIANT_PGRAPH && !(idx->graph_p >= 0.2f && idx->graph_p <= 2.0f))
+        return fail(err, UHNSW_EINVAL, "graph_p=%g outside [0.2, 2]", (double)idx->graph_p);
     for (int i = 0; i < 2; ++i) {
         int r = check_graph(err, idx->graphs[i], idx->n, i);
         if (r) return r;
@@ -707,6 +718,7 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     c->d = idx->d;
     c->storage = idx->storage;
     c->variant = idx->variant;
+    c->graph_p = idx->variant == UHNSW_VARIANT_PGRAPH ? idx->graph_p : 0.0f;
     c->l05_fast = c->l05_table = true;
     for (int64_t i = 0; i < n * idx->d && (c->l05_fast || c->l05_table); ++i) {
         const float v = idx->base[i];
@@ -852,9 +864,15 @@ static int search_on(uhnsw_ctx *c, uhnsw_ctx::StreamSet *S, const float *queries
     a.nq = nq;
     a.k_max = k_max;
     a.ef_max = ef_max;
-    // Sec. 3.1's 1.4, or Sec. 4.5's 0.6 for the extended pair
-    a.cutoff = prm.cutoff > 0.0f ? prm.cutoff : (c->variant == UHNSW_VARIANT_EXT ? 0.6f : 1.4f);
-    a.ext = c->variant == UHNSW_VARIANT_EXT;
+    // Sec. 3.1's 1.4, Sec. 4.5's 0.6 for the extended pair; the per-p graph
+    // takes every query
+    a.cutoff = prm.cutoff > 0.0f ? prm.cutoff
+               : c->variant == UHNSW_VARIANT_EXT ? 0.6f
+               : c->variant == UHNSW_VARIANT_PGRAPH ? INFINITY
+                                                     : 1.4f;
+    a.ext = c->variant != UHNSW_VARIANT_STD;
+    a.walk_p = c->graph_p;
+    p_range(c->variant, &a.p_lo, &a.p_hi);
     a.l05_fast = c->l05_fast;
     a.l05_table = c->l05_table;
     a.t_param = prm.t;
@@ -1330,7 +1348,8 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     for (int64_t i = 0; i < nq; ++i) {
         if (!std::isfinite(p[i]) || !p_in_range(c->variant, p[i]))
             return fail(c, UHNSW_EINVAL, "p[%lld]=%g outside %s", (long long)i, (double)p[i],
-                        c->variant == UHNSW_VARIANT_EXT ? "[0.2, 1]" : "[0.5, 2]");
+                        c->variant == UHNSW_VARIANT_EXT ? "[0.2, 1]"
+                        : c->variant == UHNSW_VARIANT_PGRAPH ? "[0.2, 2]" : "[0.5, 2]");
         if (k[i] < 1 || k[i] > UHNSW_KMAX)
             return fail(c, UHNSW_EINVAL, "k[%lld]=%d outside [1, %d]", (long long)i, k[i], UHNSW_KMAX);
         if (ef[i] < k[i] || ef[i] > UHNSW_EFMAX)

@@ -79,8 +79,9 @@ struct SearchArgs {
     const int32_t *entry;   // [nq] layer-0 entry node
     const float *ekey;      // [nq] its base-metric key
     const int32_t *dnb;     // [nq] base distances the descent computed
-    // index variant: 0 = G1 (L1) / G2 (L2), 1 = G_0.5 (L0.5) / G_1 (L1);
-    // picks the kernel instantiation, read on the host only
+    // index variant: 0 = G1 (L1) / G2 (L2), 1 = G_0.5 (L0.5) / G_1 (L1) and
+    // the per-p variant (walk_p > 0); picks the kernel instantiation, read
+    // on the host only
     int32_t ext;
     // every base value is 0 or at least 2^-72 in magnitude (the extended
     // walk may then take the short correctly rounded root)
@@ -88,6 +89,11 @@ struct SearchArgs {
     // every base value is an integer in [0, 255] (the extended walk may then
     // read its roots from a table)
     int32_t l05_table;
+    // the per-p variant (ext = 1 kernels): graph 0 is walked under
+    // sum |x - q|^walk_p; 0 for the other variants
+    float walk_p;
+    // the index variant's p range (queries outside are flagged UHNSW_QBAD)
+    float p_lo, p_hi;
 };
 
 // Cost-ordered launch: a pre-pass descends every query and orders the

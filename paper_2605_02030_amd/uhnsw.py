@@ -21,8 +21,8 @@ UHNSW_NOALLOC_SCRATCH_BYTES = 64 << 20
 STORE_F32, STORE_BF16, STORE_F16 = 0, 1, 2
 UHNSW_QBAD, UHNSW_QCAP = 1, 2
 UHNSW_TUNE_BEAM, UHNSW_TUNE_PIPELINED = 1, 2
-VARIANT_STD, VARIANT_EXT = 0, 1
-METRIC_L1, METRIC_L2, METRIC_L05 = 1, 2, 3
+VARIANT_STD, VARIANT_EXT, VARIANT_PGRAPH = 0, 1, 2
+METRIC_L1, METRIC_L2, METRIC_L05, METRIC_LP = 1, 2, 3, 4
 
 EXPORTS = ("uhnsw_default_params", "uhnsw_create", "uhnsw_destroy", "uhnsw_last_error", "uhnsw_load_graphs",
            "uhnsw_search", "uhnsw_search_device", "uhnsw_get_layout", "uhnsw_last_timing", "uhnsw_device_info",
@@ -49,7 +49,7 @@ class uhnsw_graph(ctypes.Structure):
 
 class uhnsw_index(ctypes.Structure):
     _fields_ = [("n", _I64), ("d", _I32), ("base", _P), ("storage", _I32), ("graphs", uhnsw_graph * 2),
-                ("variant", _I32)]
+                ("variant", _I32), ("graph_p", ctypes.c_float)]
 
 
 class uhnsw_params(ctypes.Structure):
@@ -128,7 +128,8 @@ uhnsw_check_index_files = _sig("uhnsw_check_index_files", ctypes.c_int,
 
 
 uhnsw_build_graph = _sig("uhnsw_build_graph", ctypes.c_int,
-                         [_P, _P, _I64, _I32, _I32, _I32, _I32, ctypes.c_uint64, _I32, ctypes.POINTER(_P)])
+                         [_P, _P, _I64, _I32, _I32, ctypes.c_float, _I32, _I32, ctypes.c_uint64, _I32,
+                          ctypes.POINTER(_P)])
 uhnsw_built_graph_view = _sig("uhnsw_built_graph_view", ctypes.c_int,
                               [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64)])
 uhnsw_built_graph_free = _sig("uhnsw_built_graph_free", None, [_P])
@@ -176,10 +177,10 @@ def _graph_struct(g, keep):
     return s
 
 
-def index_struct(base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD):
+def index_struct(base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD, graph_p: float = 0.0):
     """The uhnsw_index for (base, g1, g2) and the arrays it points into (keep
     them alive while the struct is used). With VARIANT_EXT, g1 / g2 are
-    G_0.5 / G_1."""
+    G_0.5 / G_1; with VARIANT_PGRAPH g1 is G_p built for graph_p."""
     base = np.ascontiguousarray(base, np.float32)
     keep = [base]
     idx = uhnsw_index()
@@ -187,6 +188,7 @@ def index_struct(base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_
     idx.base = base.ctypes.data
     idx.storage = storage
     idx.variant = variant
+    idx.graph_p = float(graph_p)
     idx.graphs[0] = _graph_struct(g1, keep)
     idx.graphs[1] = _graph_struct(g2, keep)
     return idx, keep
@@ -234,11 +236,13 @@ class Context:
         if rc != UHNSW_OK:
             raise UhnswError(rc, uhnsw_last_error(self.h).decode())
 
-    def load_graphs(self, base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD) -> None:
+    def load_graphs(self, base, g1, g2, storage: int = STORE_F32, variant: int = VARIANT_STD,
+                    graph_p: float = 0.0) -> None:
         """base: (n, d) FP32; g1 / g2: graphs with M, max_level, entry, levels,
         layers[l].nodes / row_ptr / col (G1 under L1, G2 under L2; with
-        VARIANT_EXT, G_0.5 under L0.5 and G_1 under L1)."""
-        idx, keep = index_struct(base, g1, g2, storage, variant)
+        VARIANT_EXT, G_0.5 under L0.5 and G_1 under L1; with VARIANT_PGRAPH,
+        G_p built for graph_p and a graph walked under L2)."""
+        idx, keep = index_struct(base, g1, g2, storage, variant, graph_p)
         self._check(uhnsw_load_graphs(self.h, ctypes.byref(idx)))
         self.n, self.d = int(idx.n), int(idx.d)
         del keep
@@ -402,14 +406,14 @@ class BuiltGraph:
 
 
 def build_graph(ctx: "Context", base, metric: int, M: int = 16, ef_construction: int = 200, seed: int = 0,
-                batch_max: int = 1024) -> BuiltGraph:
+                batch_max: int = 1024, metric_p: float = 0.0) -> BuiltGraph:
     """uhnsw_build_graph on ctx's device: one HNSW graph of `base` under
-    `metric` (METRIC_L1, METRIC_L2, METRIC_L05)."""
+    `metric` (METRIC_L1, METRIC_L2, METRIC_L05, or METRIC_LP with metric_p)."""
     base = np.ascontiguousarray(base, np.float32)
     n, d = base.shape
     h = _P()
-    ctx._check(uhnsw_build_graph(ctx.h, base.ctypes.data, n, d, int(metric), int(M), int(ef_construction),
-                                 int(seed), int(batch_max), ctypes.byref(h)))
+    ctx._check(uhnsw_build_graph(ctx.h, base.ctypes.data, n, d, int(metric), float(metric_p), int(M),
+                                 int(ef_construction), int(seed), int(batch_max), ctypes.byref(h)))
     try:
         view = uhnsw_graph()
         sec, nb = ctypes.c_double(), _I64()

@@ -64,7 +64,7 @@ def test_struct_layouts_match_c(lib, tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
     src = tmp_path / "layout.c"
-    fields = {"uhnsw_index": ["n", "d", "base", "storage", "graphs", "variant"],
+    fields = {"uhnsw_index": [f for f, _ in lib.uhnsw_index._fields_],
               "uhnsw_params": [f for f, _ in lib.uhnsw_params._fields_],
               "uhnsw_graph": ["M", "max_level", "entry_point", "level", "n_nodes", "nodes", "row_ptr", "col"],
               "uhnsw_serve_config": [f for f, _ in lib.uhnsw_serve_config._fields_],

@@ -1,0 +1,102 @@
+"""The per-p HNSW baseline (the U-HNSW paper's Sec. 4.3, Fig. 4) on the GPU:
+a graph G_p built for one p (uhnsw_build_graph, metric 4) and walked under
+sum |x - q|^p (v_log / v_exp), against the oracle walking the same graph
+under the same key with FP64 terms.
+
+Parity rule for this walk: its keys are transcendental, so the GPU's FP32
+keys and the oracle's differ in the last bits and the two walks may take a
+different turn where two keys are that close. C must be identical except in
+such rows, which must stay few; in every row the returned top-K is checked
+by the usual near-tie rule against the oracle's verification of the GPU's
+own C (the L_p sums of a given C do not depend on the walk)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from parity import check_row, lp_sums64  # noqa: E402
+from test_gpu_parity import _say, run_device  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+
+    assert torch.cuda.is_available()
+    return torch
+
+
+@pytest.mark.parametrize("p0", [0.7, 1.2, 1.8])
+def test_pgraph_walk_parity(torch_cuda, wl1, p0):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, _, g2 = wl1
+    ctx = uhnsw.Context(0)
+    try:
+        gp = uhnsw.build_graph(ctx, wl.base, uhnsw.METRIC_LP, M=16, ef_construction=200, seed=5, metric_p=p0)
+        ctx.load_graphs(wl.base, gp, g2, variant=uhnsw.VARIANT_PGRAPH, graph_p=p0)
+        g, v = ctx.layout()
+        p = np.full(wl.nq, p0, np.float32)
+        ef = np.full(wl.nq, 64, np.int32)
+        gpu = run_device(torch_cuda, ctx, wl.queries, p, wl.k, ef, 10, 64)
+        fused = run_device(torch_cuda, ctx, wl.queries, p, wl.k, ef, 10, 64, params=uhnsw.default_params(fused=1))
+    finally:
+        ctx.close()
+    for j in (0, 1, 3, 4):  # two-kernel and fused forms agree bit for bit (ids, dists, C)
+        np.testing.assert_array_equal(gpu[j], fused[j])
+    for f in ("graph", "n_b", "n_exp", "n_p", "nc", "entry0"):
+        np.testing.assert_array_equal(gpu[2][f], fused[2][f])
+    ids, dists, st, cid, ckey = gpu
+    G, G2 = oracle.Graph(gp), oracle.Graph(g2)
+    D = oracle.Data(wl.base)
+    prm = oracle.Params(g=g, v=v, variant=oracle.VARIANT_PGRAPH, walk_p=p0, cutoff=1e30)
+    o = oracle.query_batch(G, G2, D, wl.queries, p, wl.k, ef, prm, k_stride=10, c_stride=64)
+    assert (st["graph"] == 1).all() and (st["flags"] == 0).all()
+    same_c = [bool((cid[i] == o["c_ids"][i]).all()) for i in range(wl.nq)]
+    # where C is the same, its FP32 keys agree to within the term error
+    for i in np.flatnonzero(same_c):
+        nc = int(st["nc"][i])
+        np.testing.assert_allclose(ckey[i, :nc], o["c_keys"][i, :nc], rtol=2e-5)
+    # verified rows: the GPU's C run through the oracle's verification
+    n_exc = 0
+    for i in range(wl.nq):
+        C = cid[i][cid[i] >= 0]
+        K = int(wl.k[i])
+        orc_ids, _, _, ost = oracle.verify(D, wl.queries[i], p0, K, C, max(K, 2), oracle.m_of(0.92, K))
+        r, gap = check_row(wl.base, wl.queries[i], p0, K, max(K, 2), oracle.m_of(0.92, K), cid[i], ids[i],
+                           dists[i], int(st["n_p"][i]), np.asarray(orc_ids, np.int64), int(ost.n_p))
+        n_exc += r == "excused"
+    # where the walks took different turns: at a near tie of the two key sets
+    gaps = []
+    for i in np.flatnonzero(~np.array(same_c)):
+        j = int(np.argmax(cid[i] != o["c_ids"][i]))
+        a, b = int(cid[i][j]), int(o["c_ids"][i][j])
+        if a < 0 or b < 0:
+            gaps.append(np.inf)
+            continue
+        sa, sb = lp_sums64(wl.base, wl.queries[i], np.array([a, b]), p0)
+        gaps.append(abs(sa - sb) / max(sa, sb))
+    _say(f"per-p graph p={p0}: {sum(same_c)}/{wl.nq} rows with identical C; first-divergence FP64 gaps "
+         f"{[f'{x:.1e}' for x in gaps]}; {n_exc} verified rows excused by near ties")
+    assert sum(same_c) >= 0.9 * wl.nq
+    assert all(x <= 1e-5 for x in gaps)
+
+
+def test_pgraph_refusals(torch_cuda, wl1):
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl1
+    ctx = uhnsw.Context(0)
+    try:
+        for gp in (0.0, 0.1, 2.5, float("nan")):
+            with pytest.raises(uhnsw.UhnswError) as e:
+                ctx.load_graphs(wl.base, g1, g2, variant=uhnsw.VARIANT_PGRAPH, graph_p=gp)
+            assert e.value.code == uhnsw.UHNSW_EINVAL
+        ctx.load_graphs(wl.base, g1, g2, variant=uhnsw.VARIANT_PGRAPH, graph_p=1.0)
+        with pytest.raises(uhnsw.UhnswError):
+            ctx.search(wl.queries[:2], np.array([0.1, 1.0], np.float32), wl.k[:2], wl.ef[:2])
+        ids, _, st = ctx.search(wl.queries[:2], np.array([0.2, 2.0], np.float32), wl.k[:2], wl.ef[:2])
+        assert (st["flags"] == 0).all() and (ids[:, 0] >= 0).all()
+    finally:
+        ctx.close()
