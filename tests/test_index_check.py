@@ -130,9 +130,16 @@ def test_base_and_sizes_refused(lib, small):
     assert _check(lib, bad, g1, g2)[0] == lib.UHNSW_EINVAL
     rc, msg = _check(lib, wl.base, g1, g2, storage=3)
     assert rc == lib.UHNSW_EINVAL and "storage" in msg
-    idx, keep = lib.index_struct(wl.base, g1, g2, variant=2)
+    idx, keep = lib.index_struct(wl.base, g1, g2, variant=3)
     rc, msg = lib.check_index(idx)
     assert rc == lib.UHNSW_EINVAL and "variant" in msg
+    idx.variant = lib.VARIANT_PGRAPH  # the per-p variant needs the p its graph was built for
+    for gp in (0.0, 0.1, 2.5, float("nan")):
+        idx.graph_p = gp
+        rc, msg = lib.check_index(idx)
+        assert rc == lib.UHNSW_EINVAL and "graph_p" in msg, (gp, msg)
+    idx.graph_p = 0.7
+    assert lib.check_index(idx) == (lib.UHNSW_OK, "")
     idx.variant = lib.VARIANT_EXT  # any structurally valid pair is accepted for either variant
     assert lib.check_index(idx) == (lib.UHNSW_OK, "")
     del keep
