@@ -112,7 +112,11 @@ typedef struct {
     int32_t t;                /* candidates; 0 -> min(ef, 6K), else min(ef,t) */
     int32_t kappa;            /* batch size; 0 -> max(K, 2)                   */
     int32_t beam_width;       /* nodes expanded per walk step, 1 = HNSW       */
-    int32_t early_abort;      /* exact partial-sum abort in verification      */
+    int32_t early_abort;      /* exact partial-sum abort in verification: for
+                                 rows of more than 256 dimensions the second
+                                 half of a row is read only while its partial
+                                 sum is at most the K-th best of R; shorter
+                                 rows are always read whole                   */
     int32_t visited_slots;    /* LDS visited-cache slots; 0 -> the largest
                                  power of two in 1,024 .. 8,192 that keeps a
                                  wave's LDS within 12 KiB (8,192 above ef
@@ -158,6 +162,9 @@ typedef struct {
     uint32_t t_end;
     int32_t n_up;             /* base distances of the upper-layer descent
                                  (part of n_b; the rest are layer 0's)        */
+    int32_t n_cut;            /* L_p rows (of n_p) whose second half was not
+                                 read: the partial-sum abort (early_abort,
+                                 rows of more than 256 dimensions)            */
 } uhnsw_stats;
 
 /* Fill *prm with the defaults above. */

@@ -121,9 +121,7 @@ __device__ int search_layer(const BuildArgs &A, const BLds &L, const float (&qv)
     if (lane == 0) {
         L.Wk[0] = dep;
         L.Wi[0] = (uint32_t)ep;
-        uint32_t s0, t0;
-        L.vis.locate(ep, s0, t0);
-        L.vis.mark(s0, t0);
+        L.vis.mark_first(ep);
     }
     wave_sync();
     int nW = 1, lb = 0;
@@ -204,7 +202,7 @@ __device__ int heuristic(const BuildArgs &A, const BLds &L, const float *Ck, con
 // v's own list on that layer and to the plan (for the reverse links).
 template <int NCH, int MET>
 __global__ void __launch_bounds__(64) build_plan_kernel(BuildArgs A) {
-    extern __shared__ char lds[];
+    extern __shared__ __attribute__((aligned(16))) char lds[];
     const BLds L = build_lds(lds, A);
     const int i = blockIdx.x;
     if (i >= A.b) return;
@@ -261,7 +259,7 @@ __global__ void __launch_bounds__(64) build_plan_kernel(BuildArgs A) {
 // the new one, ascending by distance to u, with the same heuristic.
 template <int NCH, int MET>
 __global__ void __launch_bounds__(64) build_link_kernel(BuildArgs A) {
-    extern __shared__ char lds[];
+    extern __shared__ __attribute__((aligned(16))) char lds[];
     const BLds L = build_lds(lds, A);
     const int g = blockIdx.x;
     if (g >= A.ng) return;

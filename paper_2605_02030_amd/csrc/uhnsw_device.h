@@ -48,11 +48,33 @@ __device__ __forceinline__ bool key_less(float ka, uint32_t ia, float kb, uint32
     return ka < kb || (ka == kb && ia < ib);
 }
 
-// Pairwise combine inside a G-lane group; lane l < o receives s_l + s_{l+o}.
+// Pairwise combine inside a G-lane group; lane l < o receives s_l + s_{l+o}
+// (o = G/2 .. 1), every lane of the group ends with the group's sum.
 template <int G>
 __device__ __forceinline__ float group_sum(float s) {
 #pragma unroll
     for (int o = G / 2; o >= 1; o >>= 1) s = s + __shfl_xor(s, o, kWave);
+    return s;
+}
+
+// The same combine, in the same order, where only lane 0 of each group needs
+// the sum (the other lanes end with partial values): steps inside a 16-lane
+// row read lane l + o with a DPP row shift, one VALU instruction each, and
+// no LDS round trip; wider steps use a cross-lane permute.
+template <int O>
+__device__ __forceinline__ float shift_down(float s) {
+    if constexpr (O >= 16)
+        return __shfl_down(s, O, kWave);
+    else  // row_shl:O (DPP control 0x100 + O): lane l reads lane l + O of its row
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), 0x100 + O, 0xF, 0xF, true));
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum_lane0(float s) {
+    if constexpr (G > 1) {
+        s = s + shift_down<G / 2>(s);
+        return group_sum_lane0<G / 2>(s);
+    }
     return s;
 }
 
@@ -171,21 +193,24 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
     for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
+        // row-steps holding at least one row (a wave-uniform count): the
+        // others are neither loaded nor summed. Lanes past the last row load
+        // a copy of it (the same lines as its own group, so no extra
+        // traffic) and their sums are dropped.
+        const int left = nrows - r0;
         typename E::Raw raw[RB][NCH];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            const int row = r0 + b * RPW + grp;
-            if (row < nrows) {
+            if (b == 0 || b * RPW < left) {
+                const int row = min(r0 + b * RPW + grp, nrows - 1);
                 const T *rp = base + (int64_t)ids[row] * pitch + gl * V;
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) raw[b][c] = E::load(rp + c * G * V);
-            } else {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c) raw[b][c] = E::zero();
             }
         }
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
+            if (!(b == 0 || b * RPW < left)) break;
             float s = 0.0f;
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
@@ -208,7 +233,7 @@ __device__ __forceinline__ void rows_base_dist(const T *__restrict__ base, int64
                         s = s + sqrtf(fabsf(dlt));  // correctly rounded root
                 }
             }
-            s = group_sum<G>(s);
+            s = group_sum_lane0<G>(s);
             const int row = r0 + b * RPW + grp;
             if (row < nrows && gl == 0) keys[row] = s;
         }
@@ -391,14 +416,19 @@ __device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const
 }
 
 // Visited cache: a direct-mapped table in LDS that never reports a node as
-// visited unless it was (it may forget; duplicates are then dropped against
-// W). Two slot formats:
-//  * 32-bit slots holding the id (-1 empty), slot = multiplicative hash;
+// visited unless it was (it may forget; a forgotten node is gathered again
+// and dropped against W, or is worse than W's last entry). Two slot formats:
 //  * 16-bit slots when ids fit in kbits <= bits + 15: h = id * odd mod 2^kbits
 //    is a bijection on kbits-bit values, the top `bits` of h pick the slot and
 //    the remaining bits + 1 are stored (0 empty) -- slot and stored value
 //    together identify the id, so the table is still exact, at half the LDS
-//    per slot.
+//    per slot;
+//  * 32-bit slots holding the id (-1 empty), slot = multiplicative hash.
+// The probe is one narrow LDS read on the expansion's critical path. (An
+// 8-way set-associative table of 16-bit tags in the same 8 KiB, one 16-byte
+// read per probe, gathers 11 % fewer rows at ef 256 on the 1M x 128
+// workload, but its wider read and tag compare lengthen every expansion, and
+// the walk, bound by the latency of that chain, ran 3-9 % slower.)
 struct VisCache {
     void *base;
     int bits, kbits;
@@ -428,6 +458,12 @@ struct VisCache {
             reinterpret_cast<uint16_t *>(base)[slot] = (uint16_t)tag;
         else
             reinterpret_cast<uint32_t *>(base)[slot] = tag;
+    }
+    // the first node of a walk, into an empty cache
+    __device__ __forceinline__ void mark_first(int32_t id) const {
+        uint32_t s, t;
+        locate(id, s, t);
+        mark(s, t);
     }
 };
 
@@ -549,7 +585,7 @@ __device__ __forceinline__ void load_query(const float *q, int d, float (&qv)[NC
 }
 
 template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER, bool EXT>
-__device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
+__device__ __forceinline__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
     const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits, A.vis_kbits);
@@ -579,7 +615,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         if (lane == 0) {
             if (A.ncand) A.ncand[qi] = -1;
             st->graph = 0;
-            st->n_b = st->n_exp = st->n_p = st->batches = st->nc = st->n_up = 0;
+            st->n_b = st->n_exp = st->n_p = st->batches = st->nc = st->n_up = st->n_cut = 0;
             st->flags = UHNSW_QBAD;
             st->entry0 = -1;
             st->t_begin = st->t_end = t_begin;
@@ -619,9 +655,7 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     if (lane == 0) {
         L.Wk[0] = kcur;
         L.Wi[0] = (uint32_t)cur;
-        uint32_t s0, t0;
-        L.vis.locate(cur, s0, t0);
-        L.vis.mark(s0, t0);
+        L.vis.mark_first(cur);
     }
     wave_sync();
     int nW = 1, lb = 0, n_exp = 0, flags = 0;
@@ -679,14 +713,17 @@ __device__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
         } else if (which < npick) {
             nb = Gr.adj0[(int64_t)(which == 0 ? node0 : node1) * M0 + slot];
         }
+        // probe, then mark what was not there: one LDS read and one write per
+        // lane, each issued for all lanes at once, so every probe sees the
+        // cache as it was before this step's marks
         bool fresh = false;
-        uint32_t vs = 0, vt = 0;
         if (nb >= 0) {
+            uint32_t vs, vt;
             L.vis.locate(nb, vs, vt);
             fresh = !L.vis.seen(vs, vt);
+            if (fresh) L.vis.mark(vs, vt);
         }
         wave_sync();
-        if (fresh) L.vis.mark(vs, vt);
         const uint64_t fm = ballot(fresh);
         const int nnew = popc64(fm);
         if (nnew == 0) continue;
@@ -764,7 +801,7 @@ template <typename T>
 constexpr int walk_rb_vgprs() { return sizeof(T) == 4 ? 64 : 32; }
 template <int G, int NCH, typename T, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_waves_per_eu<T, G>(), 8))) walk_kernel(SearchArgs A) {
-    extern __shared__ char lds_all[];
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
@@ -795,57 +832,107 @@ __device__ __forceinline__ float lp_acc(float s, float dlt, float p) {
     return s + __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(a));
 }
 
-// S[r] = sum |x - q|^p for the FP32 rows ids[r]; with abort set, S > thr is
-// reported as +inf (such a row cannot enter the top K).
-template <int G, int NCH, int PC>
-__device__ __forceinline__ void rows_lp(const float *__restrict__ base, int64_t pitch, const int32_t *ids,
-                                        int nrows, const float (&qv)[NCH][4], float p, float thr, bool abort,
-                                        float *S) {
+// S[r] = sum |x - q|^p for the FP32 rows ids[r]. Every term is nonnegative
+// and FP32 addition is monotone, so a partial sum (each lane's first chunks,
+// combined over the group in the same pairwise order) never exceeds the full
+// sum S; a row whose partial sum is already above thr (the K-th smallest S of
+// R) cannot enter the top K. SPLIT (rows spread over 32 or 64 lanes, d > 256,
+// four chunks per lane, abort on): the first half of each row is loaded and
+// summed, and the second half is fetched only for rows whose partial sum is
+// still at most thr; a row stopped there, or whose full S exceeds thr, is
+// reported as +inf. Otherwise rows are loaded whole in one step and summed in
+// full (rows of up to 256 dimensions: their few bytes are in flight together).
+template <int G, int NCH, int PC, bool SPLIT>
+__device__ __forceinline__ int rows_lp_impl(const float *__restrict__ base, int64_t pitch, const int32_t *ids,
+                                             int nrows, const float (&qv)[NCH][4], float p, float thr, float *S) {
     constexpr int V = 4;
     constexpr int RPW = kWave / G;
     // verification batches are small (kappa rows): two row-steps in flight
     constexpr int RB = (32 / (NCH * V)) > 0 ? (32 / (NCH * V)) : 1;
+    constexpr int H = SPLIT ? NCH / 2 : NCH;  // chunks loaded before the abort test
     const int lane = lane_id();
     const int grp = lane / G, gl = lane % G;
+    int cut = 0;  // rows whose second half was not read
     for (int r0 = 0; r0 < nrows; r0 += RPW * RB) {
         float x[RB][NCH][V];
+        const float *rp[RB];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
             const int row = r0 + b * RPW + grp;
-            if (row < nrows) {
-                const float *rp = base + (int64_t)ids[row] * pitch + gl * V;
+            rp[b] = row < nrows ? base + (int64_t)ids[row] * pitch + gl * V : nullptr;
 #pragma unroll
-                for (int c = 0; c < NCH; ++c) Elem<float>::load4(rp + c * G * V, x[b][c]);
-            } else {
-#pragma unroll
-                for (int c = 0; c < NCH; ++c)
+            for (int c = 0; c < H; ++c) {
+                if (rp[b])
+                    Elem<float>::load4(rp[b] + c * G * V, x[b][c]);
+                else
 #pragma unroll
                     for (int e = 0; e < V; ++e) x[b][c][e] = qv[c][e];
             }
         }
+        float s[RB];
 #pragma unroll
         for (int b = 0; b < RB; ++b) {
-            float s = 0.0f;
+            s[b] = 0.0f;
 #pragma unroll
-            for (int c = 0; c < NCH; ++c)
+            for (int c = 0; c < H; ++c)
 #pragma unroll
-                for (int e = 0; e < V; ++e) s = lp_acc<PC>(s, x[b][c][e] - qv[c][e], p);
-            s = group_sum<G>(s);
+                for (int e = 0; e < V; ++e) s[b] = lp_acc<PC>(s[b], x[b][c][e] - qv[c][e], p);
+        }
+        bool live[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) live[b] = true;
+        if (SPLIT) {
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                // the group's partial sum, the same value on every lane of it
+                live[b] = rp[b] != nullptr && !(group_sum<G>(s[b]) > thr);
+                cut += popc64(ballot(gl == 0 && rp[b] != nullptr && !live[b]));
+#pragma unroll
+                for (int c = H; c < NCH; ++c) {
+                    if (live[b])
+                        Elem<float>::load4(rp[b] + c * G * V, x[b][c]);
+                    else
+#pragma unroll
+                        for (int e = 0; e < V; ++e) x[b][c][e] = qv[c][e];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+#pragma unroll
+                for (int c = H; c < NCH; ++c)
+#pragma unroll
+                    for (int e = 0; e < V; ++e) s[b] = lp_acc<PC>(s[b], x[b][c][e] - qv[c][e], p);
+        }
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const float t = group_sum_lane0<G>(s[b]);
             const int row = r0 + b * RPW + grp;
-            if (row < nrows && gl == 0) S[row] = (abort && s > thr) ? INFINITY : s;
+            if (row < nrows && gl == 0) S[row] = (SPLIT && (!live[b] || t > thr)) ? INFINITY : t;
         }
     }
+    return cut;
+}
+
+// Returns the number of rows whose second half the abort left unread.
+template <int G, int NCH, int PC>
+__device__ __forceinline__ int rows_lp(const float *__restrict__ base, int64_t pitch, const int32_t *ids,
+                                       int nrows, const float (&qv)[NCH][4], float p, float thr, bool abort,
+                                       float *S) {
+    if constexpr (G >= 32 && NCH >= 2) {
+        if (abort) return rows_lp_impl<G, NCH, PC, true>(base, pitch, ids, nrows, qv, p, thr, S);
+    }
+    return rows_lp_impl<G, NCH, PC, false>(base, pitch, ids, nrows, qv, p, thr, S);
 }
 
 template <int G, int NCH>
-__device__ __forceinline__ void lp_dists(int pc, const float *base, int64_t pitch, const int32_t *ids, int nrows,
-                                         const float (&qv)[NCH][4], float p, float thr, bool abort, float *S) {
+__device__ __forceinline__ int lp_dists(int pc, const float *base, int64_t pitch, const int32_t *ids, int nrows,
+                                        const float (&qv)[NCH][4], float p, float thr, bool abort, float *S) {
     switch (pc) {
-        case 1: rows_lp<G, NCH, 1>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
-        case 2: rows_lp<G, NCH, 2>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
-        case 3: rows_lp<G, NCH, 3>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
-        case 4: rows_lp<G, NCH, 4>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
-        default: rows_lp<G, NCH, 0>(base, pitch, ids, nrows, qv, p, thr, abort, S); break;
+        case 1: return rows_lp<G, NCH, 1>(base, pitch, ids, nrows, qv, p, thr, abort, S);
+        case 2: return rows_lp<G, NCH, 2>(base, pitch, ids, nrows, qv, p, thr, abort, S);
+        case 3: return rows_lp<G, NCH, 3>(base, pitch, ids, nrows, qv, p, thr, abort, S);
+        case 4: return rows_lp<G, NCH, 4>(base, pitch, ids, nrows, qv, p, thr, abort, S);
+        default: return rows_lp<G, NCH, 0>(base, pitch, ids, nrows, qv, p, thr, abort, S);
     }
 }
 
@@ -893,7 +980,7 @@ __device__ inline VerifyLds verify_lds(char *p, int kv_cap) {
 // Verification of one query. C comes from global memory (Cg) or, in the
 // fused kernel, straight from the walk's list in LDS (Cl, expanded bit set).
 template <int G, int NCH>
-__device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, const int32_t *Cg,
+__device__ __forceinline__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, const int32_t *Cg,
                            const uint32_t *Cl) {
     const int lane = lane_id();
     const float p = A.p[qi];
@@ -935,14 +1022,14 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, c
     int dummy_min, dummy_in;
     int nr = merge_into_sorted<false>(L.Rk, L.Ri, 0, K, L.Bk, L.Bi, nR, L.Ulo, L.Urank, L.Slo, false, &dummy_min,
                                &dummy_in);
-    int pos = nR, batches = 0;
+    int pos = nR, batches = 0, n_cut = 0;
     while (pos < nc) {
         const int nb = nc - pos < kappa ? nc - pos : kappa;
         const float thr = L.Rk[nr - 1];
         wave_sync();
         for (int i = lane; i < nb; i += kWave) L.Bi[i] = Cl ? (int32_t)(Cl[pos + i] & kIdMask) : Cg[pos + i];
         wave_sync();
-        lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nb, qv, p, thr, A.early_abort != 0, L.Bk);
+        n_cut += lp_dists<G, NCH>(pc, A.f32_base, A.pitch, L.Bi, nb, qv, p, thr, A.early_abort != 0, L.Bk);
         wave_sync();
         // entries at +inf were aborted: move them out of the merge by id order
         int n_in = 0, min_new;
@@ -963,6 +1050,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, c
     }
     if (lane == 0) {
         st->n_p = pos;
+        st->n_cut = n_cut;
         st->batches = batches;
         st->t_end = (uint32_t)wall_clock64();
     }
@@ -970,7 +1058,7 @@ __device__ void verify_one(const SearchArgs &A, int64_t qi, char *lds, int nc, c
 
 template <int G, int NCH>
 __global__ void __launch_bounds__(256) verify_kernel(SearchArgs A) {
-    extern __shared__ char lds_all[];
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     const int64_t qi = (int64_t)blockIdx.x * A.waves_per_block + wave;
@@ -1005,7 +1093,7 @@ constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32
 template <int G, int NCH, typename T, int BEAM, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T, G>(), 8)))
 search_kernel(SearchArgs A) {
-    extern __shared__ char lds_all[];
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int wave = threadIdx.x / kWave;
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     const WalkLds L = walk_lds(lds, A.ef_cap, A.vis_bits, A.vis_kbits);
@@ -1042,7 +1130,7 @@ search_kernel(SearchArgs A) {
 template <int G, int NCH, typename T, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8))) descend_kernel(SearchArgs A,
                                                                                                   OrderArgs O) {
-    extern __shared__ char lds_all[];
+    extern __shared__ __attribute__((aligned(16))) char lds_all[];
     const int wave = threadIdx.x / kWave;
     const int lane = lane_id();
     constexpr int kWaveBytes = descend_lds_wave_bytes(EXT);

@@ -61,7 +61,7 @@ class uhnsw_params(ctypes.Structure):
 
 class uhnsw_stats(ctypes.Structure):
     _fields_ = [(f, _I32) for f in ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0")] + \
-               [("t_begin", ctypes.c_uint32), ("t_end", ctypes.c_uint32), ("n_up", _I32)]
+               [("t_begin", ctypes.c_uint32), ("t_end", ctypes.c_uint32), ("n_up", _I32), ("n_cut", _I32)]
 
 
 class uhnsw_serve_config(ctypes.Structure):
@@ -75,9 +75,10 @@ class uhnsw_serve_result(ctypes.Structure):
                 ("ids", _I64 * UHNSW_KMAX), ("dists", ctypes.c_float * UHNSW_KMAX)]
 
 
-STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end", "n_up")
+STATS_FIELDS = ("graph", "n_b", "n_exp", "n_p", "batches", "nc", "flags", "entry0", "t_begin", "t_end", "n_up",
+                "n_cut")
 STATS_DTYPE = np.dtype([(f, np.int32) for f in STATS_FIELDS[:8]] + [(f, np.uint32) for f in STATS_FIELDS[8:10]]
-                       + [("n_up", np.int32)])
+                       + [("n_up", np.int32), ("n_cut", np.int32)])
 STATS_WORDS = len(STATS_FIELDS)
 
 

@@ -25,7 +25,8 @@ import hashlib
 
 import numpy as np
 
-__all__ = ["Workload", "make_workload", "p_uniform", "p_uniform_ext", "P_GRID", "P_GRID_EXT", "WORKLOADS"]
+__all__ = ["Workload", "make_workload", "p_uniform", "p_uniform_ext", "P_GRID", "P_GRID_EXT", "WORKLOADS",
+           "clustered"]
 
 # p grid 0.5, 0.6, ..., 2.0 (Sec. 4.3 evaluates exactly these 16 values).
 P_GRID = np.array([(5 + j) / 10 for j in range(16)], dtype=np.float32)
@@ -208,3 +209,16 @@ def make_workload(cfg: int, n: int | None = None, nq: int | None = None,
         name = f"{name.split('-')[0]}-{_size_name(n)}-d{d}"
     return Workload(cfg=cfg, name=name, base=base, queries=queries,
                     p=p, k=k, ef=ef, graph_seed=s0 + 5)
+
+
+def clustered(n: int, nq: int, d: int, clusters: int, seed: int, spread: float = 0.05):
+    """Tight, well-separated clusters: centres N(0, 1) per coordinate, points
+    and queries centre + N(0, spread^2); queries near the first centres, in
+    turn. A search list wider than a cluster then holds members of other
+    clusters whose distances are many times the near ones'. Returns (base,
+    queries) as float32."""
+    rng = _rng(seed)
+    centres = rng.standard_normal((clusters, d))
+    base = centres[np.arange(n) % clusters] + spread * rng.standard_normal((n, d))
+    queries = centres[np.arange(nq) % clusters] + spread * rng.standard_normal((nq, d))
+    return base.astype(np.float32), queries.astype(np.float32)

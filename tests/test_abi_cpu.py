@@ -53,7 +53,7 @@ def test_struct_sizes_match_header(lib):
     assert ctypes.sizeof(lib.uhnsw_graph) == 12 + 4 + 8 + 32 * 8 * 4  # M..entry, pad, level ptr, 4 arrays
     # n, d (+pad), base, storage (+pad), two graphs, variant (+pad)
     assert ctypes.sizeof(lib.uhnsw_index) == 8 + 8 + 8 + 8 + 2 * ctypes.sizeof(lib.uhnsw_graph) + 8
-    assert lib.STATS_DTYPE.itemsize == 44
+    assert lib.STATS_DTYPE.itemsize == 48
 
 
 def test_struct_layouts_match_c(lib, tmp_path):

@@ -180,6 +180,47 @@ def test_precision_form_d960(torch_cuda, wl3_small, storage):
     compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, efa, gpu, g, v)
 
 
+def test_partial_sum_abort_d960(torch_cuda):
+    """The partial-sum abort on rows of 960 dimensions (half of each row
+    summed; the other half read only while that partial sum is at most the
+    K-th best S of R) changes no result. Input: tight clusters, with W (ef =
+    t = 128) wider than a cluster, so C ends in members of other clusters;
+    tau above 1 verifies all of C. Ids, distances, N_p and batches equal
+    those with the abort off, in both kernel forms; with it on rows are
+    really cut (n_cut > 0), with it off none are; the oracle agrees."""
+    from paper_2605_02030_amd import uhnsw
+
+    base, queries = synth.clustered(4000, 24, 960, clusters=80, seed=9301)
+    nq = len(queries)
+    p = np.array([0.5, 0.8, 1.0, 1.3, 1.6, 2.0], np.float32)[np.arange(nq) % 6]
+    k = np.full(nq, 10, np.int32)
+    efa = np.full(nq, 128, np.int32)
+    g1 = sg.build_graph(base, sg.METRIC_L1, M=16, ef_construction=100, seed=7, cache=False)
+    g2 = sg.build_graph(base, sg.METRIC_L2, M=16, ef_construction=100, seed=7, cache=False)
+    ctx = uhnsw.Context(0)
+    try:
+        ctx.load_graphs(base, g1, g2)
+        g, v = ctx.layout()
+        assert g == 64
+        for fused in (0, 1):
+            prm = dict(fused=fused, t=128, tau=2.0)
+            on = run_device(torch_cuda, ctx, queries, p, k, efa, 10, 128, params=uhnsw.default_params(**prm))
+            off = run_device(torch_cuda, ctx, queries, p, k, efa, 10, 128,
+                             params=uhnsw.default_params(early_abort=0, **prm))
+            np.testing.assert_array_equal(on[0], off[0])
+            np.testing.assert_array_equal(on[1], off[1])
+            for f in ("n_p", "batches", "n_b", "n_exp"):
+                np.testing.assert_array_equal(on[2][f], off[2][f])
+            assert (off[2]["n_cut"] == 0).all()
+            cut, n_p = int(on[2]["n_cut"].sum()), int(on[2]["n_p"].sum())
+            _say(f"fused={fused}: abort cut {cut} of {n_p} L_p rows ({cut / n_p:.1%})")
+            assert 0 < cut < n_p
+    finally:
+        ctx.close()
+    compare(base, oracle.Graph(g1), oracle.Graph(g2), oracle.Data(base), queries, p, k, efa, on, g, v, tau=2.0,
+            t_param=128)
+
+
 @pytest.fixture(scope="module")
 def wl4_small():
     wl = synth.make_workload(4, n=30_000, nq=300)
