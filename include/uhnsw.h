@@ -119,7 +119,7 @@ typedef struct {
                                  rows are always read whole                   */
     int32_t visited_slots;    /* LDS visited-cache slots; 0 -> the largest
                                  power of two in 1,024 .. 8,192 that keeps a
-                                 wave's LDS within 12 KiB (8,192 above ef
+                                 wave's LDS within 11 KiB (8,192 above ef
                                  512)                                        */
     int32_t waves_per_block;  /* 0 -> 1                                       */
     int32_t persistent;       /* schedule of the queries over the waves:

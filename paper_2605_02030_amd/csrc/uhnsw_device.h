@@ -415,6 +415,166 @@ __device__ int merge_into_sorted(float *Lk, uint32_t *Li, int nL, int cap, const
     return nn < cap ? nn : cap;
 }
 
+// ------------------------------------------------- the walk's list merge
+// (key, id) as one unsigned 64-bit value with the same order: keys are +0,
+// positive or +inf (sums of nonnegative terms), so their bits order as
+// unsigned integers; the expanded bit is not part of the id.
+__device__ __forceinline__ uint64_t pack_key(float k, uint32_t id) {
+    return ((uint64_t)__float_as_uint(k) << 32) | (id & kIdMask);
+}
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int j) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// New entries at most this many are placed one at a time by the whole wave.
+constexpr int kFewNew = 4;
+
+// Insert into the walk's list W (keys Lk, ids Li with the expanded bit, nL
+// entries ascending by (key, id)) the new entries held in registers: entry
+// (uk, ui) on each lane of the mask um, no expanded bit. Entries already in W
+// are dropped, and with dedupe_u a second copy of an id in the mask; the
+// first cap entries are kept. Returns the new size; *min_new receives the
+// smallest position a new entry took (cap if none), *n_in the number of new
+// entries now in W.
+//
+// Each new entry's insertion point: with at most kFewNew entries, the wave
+// places one entry at a time: lanes 0..31 hold every B-th entry of W (the
+// last of each block of B, B = 8 .. 64 so that 32 blocks cover W), one
+// ballot of "pivot below the entry" gives its block, one read of that block
+// (one entry per lane) and a ballot give its position and whether W holds it
+// -- two LDS round trips in all. More entries search W lane by lane. Ranks
+// among the kept entries and the shift of W's tail are counted from
+// registers (lane reads), and the tail moves in groups of up to 256 entries:
+// read together, then written.
+template <bool WIDE>
+__device__ int merge_walk(float *Lk, uint32_t *Li, int nL, int cap, float uk, uint32_t ui, uint64_t um,
+                          bool dedupe_u, int *min_new, int *n_in) {
+    const int lane = lane_id();
+    const uint64_t u = ((um >> lane) & 1ull) ? pack_key(uk, ui) : ~0ull;
+    if (dedupe_u) {  // keep the lowest lane of an id listed twice
+        bool drop = false;
+        for (uint64_t m = um; m; m &= m - 1) {
+            const int j = __builtin_ctzll(m);
+            drop = drop || (((um >> lane) & 1ull) && lane > j && readlane64(u, j) == u);
+        }
+        um &= ~ballot(drop);
+    }
+    const bool mine = (um >> lane) & 1ull;
+    *n_in = 0;
+    *min_new = cap;
+    const int nU = popc64(um);
+    if (nU == 0) return nL;
+    int lo = 0;
+    bool dup = false;
+    if (nU <= kFewNew) {
+        int B = 8;
+        while (B * 32 < nL) B <<= 1;
+        const int ppos = (lane + 1) * B - 1;
+        const uint64_t piv = (lane < 32 && ppos < nL) ? pack_key(Lk[ppos], Li[ppos]) : ~0ull;
+        uint64_t m = um;
+#pragma unroll
+        for (int jj = 0; jj < kFewNew; ++jj) {
+            if (m == 0) break;
+            const int j = __builtin_ctzll(m);
+            m &= m - 1;
+            const uint64_t uj = readlane64(u, j);
+            const int blk = popc64(ballot(piv < uj));  // pivots ascend: the ones below form a prefix
+            const int e = blk * B + lane;
+            const uint64_t w = (lane < B && e < nL) ? pack_key(Lk[e], Li[e]) : ~0ull;
+            const int loj = blk * B + popc64(ballot(w < uj));
+            const bool dj = ballot(w == uj) != 0ull;
+            if (lane == j) {
+                lo = loj;
+                dup = dj;
+            }
+        }
+    } else if (mine) {
+        int a = 0, b = nL;
+        while (WIDE && b - a >= 4) {  // three pivots read together per step
+            const int q = (b - a) >> 2;
+            const int m1 = a + q, m2 = a + 2 * q, m3 = a + 3 * q;
+            const uint64_t p1 = pack_key(Lk[m1], Li[m1]), p2 = pack_key(Lk[m2], Li[m2]), p3 = pack_key(Lk[m3], Li[m3]);
+            if (p3 < u) {
+                a = m3 + 1;
+            } else if (p2 < u) {
+                a = m2 + 1;
+                b = m3;
+            } else if (p1 < u) {
+                a = m1 + 1;
+                b = m2;
+            } else {
+                b = m1;
+            }
+        }
+        while (a < b) {
+            const int mid = (a + b) >> 1;
+            if (pack_key(Lk[mid], Li[mid]) < u)
+                a = mid + 1;
+            else
+                b = mid;
+        }
+        lo = a;
+        dup = a < nL && pack_key(Lk[a], Li[a]) == u;
+    }
+    const bool keep = mine && !dup && lo < cap;
+    const uint64_t km = ballot(keep);
+    if (km == 0) return nL;
+    const int nkeep = popc64(km);
+    // rank among the kept entries; the first position any of them takes
+    int rank = 0, first = cap;
+    for (uint64_t m = km; m; m &= m - 1) {
+        const int j = __builtin_ctzll(m);
+        rank += readlane64(u, j) < u ? 1 : 0;
+        first = min(first, __builtin_amdgcn_readlane(lo, j));
+    }
+    // move W's entries at positions >= first right by the number of kept
+    // entries placed at or before them, the top group first
+    for (int top = nL; top > first; top -= 4 * kWave) {
+        const int g0 = max(first, top - 4 * kWave);
+        float k[4];
+        uint32_t id[4];
+        int sh[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = g0 + c * kWave + lane;
+            sh[c] = 0;
+            if (i < top) {
+                k[c] = Lk[i];
+                id[c] = Li[i];
+            }
+        }
+        for (uint64_t m = km; m; m &= m - 1) {
+            const int lj = __builtin_amdgcn_readlane(lo, __builtin_ctzll(m));
+#pragma unroll
+            for (int c = 0; c < 4; ++c) sh[c] += lj <= g0 + c * kWave + lane ? 1 : 0;
+        }
+        wave_sync();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = g0 + c * kWave + lane;
+            if (i < top && i + sh[c] < cap) {
+                Lk[i + sh[c]] = k[c];
+                Li[i + sh[c]] = id[c];
+            }
+        }
+        wave_sync();
+    }
+    // place the kept entries
+    const int np = lo + rank;
+    const bool in = keep && np < cap;
+    if (in) {
+        Lk[np] = uk;
+        Li[np] = ui;
+    }
+    wave_sync();
+    *n_in = popc64(ballot(in));
+    *min_new = first;
+    const int nn = nL + nkeep;
+    return nn < cap ? nn : cap;
+}
+
 // Visited cache: a direct-mapped table in LDS that never reports a node as
 // visited unless it was (it may forget; a forgotten node is gathered again
 // and dropped against W, or is worse than W's last entry). Two slot formats:
@@ -468,13 +628,14 @@ struct VisCache {
 };
 
 // ------------------------------------------------------------------- walk
+// Per wave: W (keys, then ids), the visited cache, the new rows' ids and keys
+// (kUCap each), and for the extended index the L0.5 root table.
 struct WalkLds {
     float *Wk;
     uint32_t *Wi;
     VisCache vis;
     int32_t *Uid;
     float *Uk;
-    int32_t *Ulo, *Urank, *Slo;
     float *sqt;
 };
 
@@ -484,7 +645,7 @@ __host__ __device__ inline int vis_bytes_impl(int vis_bits, int vis_kbits) {
 
 // ext: the extended index's walk also holds the L0.5 root table
 __host__ __device__ inline int walk_lds_bytes_impl(int ef_cap, int vis_bits, int vis_kbits, bool ext) {
-    return ef_cap * 8 + vis_bytes_impl(vis_bits, vis_kbits) + kUCap * 4 * 5 + (ext ? kRootTableBytes : 0);
+    return ef_cap * 8 + vis_bytes_impl(vis_bits, vis_kbits) + kUCap * 4 * 2 + (ext ? kRootTableBytes : 0);
 }
 
 __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kbits) {
@@ -496,10 +657,7 @@ __device__ inline WalkLds walk_lds(char *p, int ef_cap, int vis_bits, int vis_kb
     L.vis.kbits = vis_kbits;
     L.Uid = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(L.vis.base) + vis_bytes_impl(vis_bits, vis_kbits));
     L.Uk = reinterpret_cast<float *>(L.Uid + kUCap);
-    L.Ulo = reinterpret_cast<int32_t *>(L.Uk + kUCap);
-    L.Urank = L.Ulo + kUCap;
-    L.Slo = L.Urank + kUCap;
-    L.sqt = reinterpret_cast<float *>(L.Slo + kUCap);  // extended walk only
+    L.sqt = L.Uk + kUCap;  // extended walk only
     return L;
 }
 
@@ -584,7 +742,7 @@ __device__ __forceinline__ void load_query(const float *q, int d, float (&qv)[NC
         }
 }
 
-template <int G, int NCH, typename T, int RBV, bool WIDE, int FILTER, bool EXT>
+template <int G, int NCH, typename T, int RBV, bool WIDE, bool EXT>
 __device__ __forceinline__ int walk_one(const SearchArgs &A, int64_t qi, char *lds) {
     const int lane = lane_id();
     const uint32_t t_begin = (uint32_t)wall_clock64();
@@ -672,17 +830,19 @@ __device__ __forceinline__ int walk_one(const SearchArgs &A, int64_t qi, char *l
         const int want = beam == 1 ? 2 : beam;
         for (int b0 = lb; b0 < nW && nseen < want; b0 += kWave) {
             const int i = b0 + lane;
-            const bool un = i < nW && !(L.Wi[i] & kExpBit);
-            uint64_t m = ballot(un);
+            const uint32_t wi = i < nW ? L.Wi[i] : kExpBit;
+            uint64_t m = ballot(!(wi & kExpBit));
             while (m && nseen < want) {
-                const int pos = b0 + __ffsll((unsigned long long)m) - 1;
+                const int l = __builtin_ctzll(m);
                 m &= m - 1;
+                // the entry is in lane l's register: no second LDS read
+                const uint32_t node = (uint32_t)__builtin_amdgcn_readlane((int)wi, l);
                 if (nseen == 0) {
-                    pos0 = pos;
-                    node0 = L.Wi[pos];
+                    pos0 = b0 + l;
+                    node0 = node;
                 } else {
-                    pos1 = pos;
-                    node1 = L.Wi[pos];
+                    pos1 = b0 + l;
+                    node1 = node;
                 }
                 ++nseen;
             }
@@ -732,32 +892,20 @@ __device__ __forceinline__ int walk_one(const SearchArgs &A, int64_t qi, char *l
         base_dists<G, NCH, T, RBV, EXT>(lo, root, L.sqt, base, pitch, L.Uid, nnew, qv, L.Uk, A.walk_p);
         wave_sync();
         n_b += nnew;
-        // With W full, a new entry not below W's last one cannot enter: keep
-        // the others, compacted in their order. Late in the walk most
-        // expansions end here with nothing to merge.
-        int nu = nnew;
-        if ((FILTER == 2 || (FILTER == 1 && npick > 1)) && nW == ef) {
-            const float wk = L.Wk[nW - 1];
-            const uint32_t wi = L.Wi[nW - 1] & kIdMask;
-            const float k = lane < nnew ? L.Uk[lane] : 0.0f;
-            const int32_t id = lane < nnew ? L.Uid[lane] : 0;
-            const bool keep = lane < nnew && key_less(k, (uint32_t)id, wk, wi);
-            const uint64_t km = ballot(keep);
-            nu = popc64(km);
-            if (nu == 0) continue;
-            if (nu < nnew) {
-                wave_sync();
-                if (keep) {
-                    const int dst = lanes_below(km);
-                    L.Uk[dst] = k;
-                    L.Uid[dst] = id;
-                }
-                wave_sync();
-            }
+        // the new entries, entry r on lane r
+        const float nk = lane < nnew ? L.Uk[lane] : 0.0f;
+        const uint32_t nid = lane < nnew ? (uint32_t)L.Uid[lane] : 0u;
+        uint64_t um = nnew >= kWave ? ~0ull : ((1ull << nnew) - 1ull);
+        // With W full, a new entry not below W's last one cannot enter. Late
+        // in the walk most expansions end here with nothing to merge.
+        if (nW == ef) {
+            const uint64_t wl = pack_key(L.Wk[nW - 1], L.Wi[nW - 1]);
+            um = ballot(lane < nnew && pack_key(nk, nid) < wl);
+            if (um == 0) continue;
         }
+        wave_sync();
         int min_new, n_in;
-        nW = merge_into_sorted<WIDE>(L.Wk, L.Wi, nW, ef, L.Uk, L.Uid, nu, L.Ulo, L.Urank, L.Slo, npick > 1, &min_new,
-                               &n_in);
+        nW = merge_walk<WIDE>(L.Wk, L.Wi, nW, ef, nk, nid, um, npick > 1, &min_new, &n_in);
         if (min_new < lb) lb = min_new;
     }
 
@@ -806,14 +954,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(walk_w
     char *lds = lds_all + (size_t)wave * A.lds_wave_bytes;
     if (A.counter == nullptr) {
         const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
-        if (k < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2, EXT>(A, A.order ? A.order[k] : k, lds);
+        if (k < A.nq) walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, EXT>(A, A.order ? A.order[k] : k, lds);
         return;
     }
     // persistent: waves take queries from the counter until it passes nq
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, 2, EXT>(A, qi, lds);
+        walk_one<G, NCH, T, walk_rb_vgprs<T>(), true, EXT>(A, qi, lds);
         k = fetch_query(A.counter);
     }
 }
@@ -1087,9 +1235,7 @@ constexpr int fused_waves_per_eu() { return G <= 16 ? 5 : (sizeof(T) == 4 ? 3 : 
 template <typename T, int G>
 constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32); }
 
-// BEAM (1 or 2, equal to A.beam) specialises the fused kernel: with two
-// nodes per step the walk drops new entries that cannot enter a full W before
-// merging; with one the same test measured slower in this larger kernel.
+// BEAM (1 or 2, equal to A.beam) specialises the fused kernel.
 template <int G, int NCH, typename T, int BEAM, bool EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fused_waves_per_eu<T, G>(), 8)))
 search_kernel(SearchArgs A) {
@@ -1102,7 +1248,7 @@ search_kernel(SearchArgs A) {
         const int64_t k = (int64_t)blockIdx.x * A.waves_per_block + wave;
         const int64_t qi = k < A.nq && A.order ? A.order[k] : k;
         if (k < A.nq) {
-            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0, EXT>(A, qi, lds);
+            const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, EXT>(A, qi, lds);
             wave_sync();
             verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         }
@@ -1111,7 +1257,7 @@ search_kernel(SearchArgs A) {
     int k = fetch_query(A.counter);
     while ((int64_t)k < A.nq) {
         const int64_t qi = A.order ? A.order[k] : k;
-        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, BEAM == 2 ? 2 : 0, EXT>(A, qi, lds);
+        const int nc = walk_one<G, NCH, T, fused_rb_vgprs<T, G>(), false, EXT>(A, qi, lds);
         wave_sync();
         verify_call<G, NCH>(A, qi, vlds, nc, L.Wi);
         wave_sync();

@@ -306,13 +306,13 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     if (slots <= 0 && ef_max > 512) {
         slots = 8192;
     } else if (slots <= 0) {
-        // The largest cache that keeps a wave's LDS within 12 KiB (13 waves
+        // The largest cache that keeps a wave's LDS within 11 KiB (14 waves
         // per CU). A larger cache forgets fewer nodes (fewer repeated
         // distances), a smaller one leaves room for more waves; measured on
-        // the 1M x 128 workload: at ef 256, 4,096 slots (11.25 KiB) beat
+        // the 1M x 128 workload: at ef 256, 4,096 slots (10.5 KiB) beat
         // 2,048 by 4 %; at ef 384 and 512, 4,096 slots would leave 12-13
         // waves per CU and 2,048 wins by 16 % and 41 %.
-        constexpr int kLdsWaveBudget = 12 * 1024;
+        constexpr int kLdsWaveBudget = 11 * 1024;
         for (slots = 8192; slots > 1024; slots /= 2) {
             int b, kb;
             vis_geometry(slots, &b, &kb);
@@ -332,8 +332,8 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
     pl->search_bytes = std::max(pl->walk_bytes, pl->ef_cap * 8 + pl->verify_bytes);
     const int per_wave = prm.fused ? pl->search_bytes : std::max(pl->walk_bytes, pl->verify_bytes);
     // one wave per block by default: LDS is granted per block, and single-
-    // wave blocks pack a CU's 160 KiB without leftovers (at 11.25 KiB per
-    // wave, four-wave blocks fit 3 per CU, 12 waves; one-wave blocks 14)
+    // wave blocks pack a CU's 160 KiB without leftovers (at 10.5 KiB per
+    // wave, four-wave blocks fit 3 per CU, 12 waves; one-wave blocks 15)
     pl->wpb = prm.waves_per_block > 0 ? prm.waves_per_block : 1;
     if (pl->wpb > 4) return fail(c, UHNSW_EINVAL, "waves_per_block %d > 4", pl->wpb);
     if ((size_t)per_wave * pl->wpb > 64 * 1024)
