@@ -41,12 +41,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# v_exp_f32 / v_log_f32 issue at half the FP32 rate on gfx950: 256 CUs x 4
+# SIMDs x 16 lanes / 2 per cycle at 2.4 GHz (lane operations per second)
+TRANS_PEAK = 256 * 4 * 16 / 2 * 2.4e9
 # HBM traffic of the walk kernel from two rocprofv3 counter passes
 # (profiles/walk_kernel_mixture-1M-d128_ef256_hbm-traffic.md): FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0 per launch, valid only for that kernel source, the host
 # code that plans its launch (cache size, block shape) and ef.
-TRAFFIC = {"kernel_sha256_prefix": "f9f0e3f19191a53a", "host_sha256_prefix": "f6175f28390487f3", "ef": 256,
-           "bytes_per_launch": 25.011e9}
+TRAFFIC = {"kernel_sha256_prefix": "a22f8760022fec07", "host_sha256_prefix": "b6b0f8104ef9cf88", "ef": 256,
+           "bytes_per_launch": 24.828e9}
 # the sources the kernels are compiled from (hashed to tie the counter traffic
 # to the code it was measured on)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_02030_amd", "csrc", f)
@@ -104,9 +107,16 @@ class Form:
         self.ef = None
         self.tuned = {}
 
-    def set_ef(self, ef):
+    def set_ef(self, ef, knobs=None):
+        """knobs (batched forms): fixed beam_width / visited_slots /
+        waves_per_block / persistent / waves_per_cu instead of the autotuner's
+        choice, e.g. to profile one configuration without the tuning launches."""
         self.ef_val = ef
         self.ef = self.torch.full((self.nq,), ef, dtype=torch_int32(self.torch), device="cuda:0")
+        if self.persistent and knobs and ef not in self.tuned:
+            t = self.uhnsw.default_params(fused=1, graph=1, **knobs)
+            self.tuned[ef] = t
+            log(f"{self.name} ef={ef}: fixed knobs {knobs}")
         if self.persistent and ef not in self.tuned:
             base = self.uhnsw.default_params(fused=1, persistent=1, graph=1)
             t = self.ctx.autotune(self.q, self.p, self.k, self.ef, 10, ef, params=base, allow_beam=True,
@@ -369,7 +379,8 @@ def run_secondary(a, torch, uhnsw, sg, synth):
     log(f"workload {wl.name}: n={wl.n} d={wl.d} nq={wl.nq} ({time.time() - t0:.1f}s)")
     gt = gt_for(wl)
     out = {"workload": wl.name, "n": wl.n, "d": wl.d, "queries": wl.nq, "forms": {}}
-    if wl.n > 2_000_000:  # too large for the CPU builder: construct G1 and G2 on the GPU
+    cached = sg.cached_graphs(wl)
+    if cached is None:  # not built on the CPU: construct G1 and G2 on the GPU (the same graphs, edge for edge)
         bctx = uhnsw.Context(0)
         graphs = []
         for metric in (sg.METRIC_L1, sg.METRIC_L2):
@@ -384,7 +395,7 @@ def run_secondary(a, torch, uhnsw, sg, synth):
                               "seconds": {"G1": round(g1.seconds, 1), "G2": round(g2.seconds, 1)},
                               "batches": g1.batches}
     else:
-        g1, g2 = sg.build_graphs(wl, cache=True, verbose=True)
+        g1, g2 = cached
     dev = torch.device("cuda:0")
     q = torch.from_numpy(wl.queries).to(dev)
     p = torch.from_numpy(wl.p).to(dev)
@@ -687,9 +698,20 @@ def main():
                          "verification ablation, the t / tau study and per-graph recall across p")
     ap.add_argument("--reduced", action="store_true",
                     help="--workload 5 at 1,000,000 of its 10,000,000 rows (CPU-built graphs)")
+    ap.add_argument("--knobs", default="",
+                    help="with --ef: the batched forms' launch knobs instead of the autotuner's, as "
+                         "beam_width=2,visited_slots=2048,waves_per_block=1,persistent=3,waves_per_cu=0")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter scaling)")
     a = ap.parse_args()
+    knobs = {}
+    for kv in filter(None, a.knobs.split(",")):
+        key, val = kv.split("=")
+        if key not in ("beam_width", "visited_slots", "waves_per_block", "persistent", "waves_per_cu"):
+            ap.error(f"--knobs: unknown knob {key}")
+        knobs[key] = int(val)
+    if knobs and not a.ef:
+        ap.error("--knobs needs --ef")
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the query path runs on a single MI355X and the library has no "
               "multi-GPU path (replicate the index per GPU and shard queries to scale).", file=sys.stderr)
@@ -741,10 +763,11 @@ def main():
         if name == "fp32":  # ceiling probes on the resident FP32 rows (512 B per row)
             probes = dict(gather_512B_gbs=round(f.ctx.probe_gather(512), 1),
                           gather_256B_gbs=round(f.ctx.probe_gather(256), 1),
-                          exp_log_lane_ops_per_s=float(f"{f.ctx.probe_transcendental():.4g}"))
+                          exp_log_lane_ops_per_s=float(f"{f.ctx.probe_transcendental():.4g}"),
+                          exp_log_peak_lane_ops_per_s=TRANS_PEAK)
             log("probes", json.dumps(probes))
         if a.ef:
-            f.set_ef(a.ef)
+            f.set_ef(a.ef, knobs=knobs)
             ef, table = a.ef, []
         else:
             ef, table = calibrate(f, gt, name, EF_GRID_EXT if ext else EF_GRID)

@@ -183,6 +183,18 @@ def build_graphs(wl, threads: int = 0, cache: bool = True, verbose: bool = False
                  for m in metrics)
 
 
+def cached_graphs(wl, extended: bool = False):
+    """The pair ``build_graphs`` would return, if both are already in the
+    cache; else None (nothing is built)."""
+    dg = hashlib.sha256(np.ascontiguousarray(wl.base).tobytes()).hexdigest()
+    metrics = (METRIC_L05, METRIC_L1) if extended else (METRIC_L1, METRIC_L2)
+    paths = [os.path.join(_cache_dir(), f"g_{_key(dg, m, wl.M, wl.ef_construction, wl.graph_seed)}.npz")
+             for m in metrics]
+    if not all(os.path.exists(p) for p in paths):
+        return None
+    return tuple(_load_file(p) for p in paths)
+
+
 def save_fbin(path: str, base: np.ndarray) -> None:
     """Base vectors as .fbin: int32 n, int32 d, then n*d FP32 row-major."""
     base = np.ascontiguousarray(base, np.float32)

@@ -26,7 +26,10 @@ def test_probes(wl1):
             with pytest.raises(uhnsw.UhnswError):
                 ctx.probe_gather(bad)
         ops = ctx.probe_transcendental()
-        # 256 CUs x 16 lanes per cycle at most 2.4 GHz is about 9.8e12
-        assert 1e11 < ops < 2e13
+        # gfx950 issues v_exp_f32 / v_log_f32 at half the FP32 rate: 256 CUs x
+        # 4 SIMDs x 16 lanes / 2 per cycle at 2.4 GHz = 19.66e12 lane-ops/s,
+        # and the probe's chains put a full-rate multiply between the two
+        # (at most 15.7e12); a quarter rate would cap it at 9.8e12
+        assert 1e11 < ops <= 19.66e12 * 1.02
     finally:
         ctx.close()
