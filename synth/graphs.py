@@ -44,7 +44,7 @@ def _load():
             build_lib()
         lib = ctypes.CDLL(_LIB)
         lib.hb_build.restype = ctypes.c_void_p
-        lib.hb_build.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+        lib.hb_build.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int]
         lib.hb_max_level.restype = ctypes.c_int
@@ -72,7 +72,7 @@ class Layer:
 
 @dataclasses.dataclass
 class Graph:
-    metric: int               # 1 -> L1 (G1), 2 -> L2 (G2), 3 -> L0.5 (G_0.5)
+    metric: int               # 1 -> L1 (G1), 2 -> L2 (G2), 3 -> L0.5 (G_0.5), 4 -> L_p for one p
     n: int
     M: int
     ef_construction: int
@@ -124,24 +124,28 @@ def _load_file(path: str) -> Graph:
 
 def build_graph(base: np.ndarray, metric: int, M: int = 16, ef_construction: int = 200,
                 seed: int = 0, threads: int = 0, cache: bool = True,
-                digest: str | None = None, verbose: bool = False, batch_max: int = 1024) -> Graph:
-    """The HNSW graph of `base` under `metric` (1 L1, 2 L2, 3 L0.5), built by
-    hnsw_build.c in insertion batches of at most `batch_max` nodes."""
+                digest: str | None = None, verbose: bool = False, batch_max: int = 1024,
+                metric_p: float = 0.0) -> Graph:
+    """The HNSW graph of `base` under `metric` (1 L1, 2 L2, 3 L0.5, 4 sum
+    |x - y|^metric_p), built by hnsw_build.c in insertion batches of at most
+    `batch_max` nodes."""
     base = np.ascontiguousarray(base, dtype=np.float32)
     n, d = base.shape
     path = None
     if cache:
         if digest is None:
             digest = hashlib.sha256(base.tobytes()).hexdigest()
-        key = _key(digest, metric, M, ef_construction, seed)
+        tag = digest if metric != METRIC_LP else f"{digest}:p{float(metric_p)!r}"
+        key = _key(tag, metric, M, ef_construction, seed)
         if batch_max != 1024:
-            key = _key(f"{digest}:b{batch_max}", metric, M, ef_construction, seed)
+            key = _key(f"{tag}:b{batch_max}", metric, M, ef_construction, seed)
         path = os.path.join(_cache_dir(), f"g_{key}.npz")
         if os.path.exists(path):
             return _load_file(path)
     lib = _load()
     t0 = time.time()
-    h = lib.hb_build(base.ctypes.data, n, d, metric, M, ef_construction, seed, threads, int(verbose), batch_max)
+    h = lib.hb_build(base.ctypes.data, n, d, metric, float(metric_p), M, ef_construction, seed, threads,
+                     int(verbose), batch_max)
     if not h:
         raise ValueError("hnsw build rejected its arguments")
     try:
@@ -171,7 +175,7 @@ def build_graph(base: np.ndarray, metric: int, M: int = 16, ef_construction: int
     return g
 
 
-METRIC_L1, METRIC_L2, METRIC_L05 = 1, 2, 3
+METRIC_L1, METRIC_L2, METRIC_L05, METRIC_LP = 1, 2, 3, 4
 
 
 def build_graphs(wl, threads: int = 0, cache: bool = True, verbose: bool = False, extended: bool = False):

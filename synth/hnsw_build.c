@@ -1,8 +1,10 @@
 /*
  * Deterministic HNSW construction for the two U-HNSW base graphs
  * (G1 under L1, G2 under L2; U-HNSW paper, Sec. 3.1), and for the extended
- * variant's G_0.5 under L0.5 (Sec. 4.5). metric: 1 = L1, 2 = squared L2,
- * 3 = sum sqrt|a - b| (ranks like L0.5).
+ * variant's G_0.5 under L0.5 (Sec. 4.5), and a graph for one fixed p (the
+ * per-p HNSW baseline of Sec. 4.3). metric: 1 = L1, 2 = squared L2,
+ * 3 = sum sqrt|a - b| (ranks like L0.5), 4 = sum |a - b|^mp for a given mp
+ * (each term taken in double and rounded to float).
  *
  * The construction itself is the HNSW algorithm the paper builds on
  * (Sec. 2.2: incremental insertion, M neighbours per node, a dynamic
@@ -45,6 +47,7 @@ static inline int pr_lt(pr_t a, pr_t b) { return a.d < b.d || (a.d == b.d && a.i
 typedef struct {
     int64_t n;
     int d, metric, M, M0, efc;
+    double mp; /* metric 4: the power */
     const float *base;
     int8_t *level;
     int max_level;
@@ -67,12 +70,13 @@ typedef struct {
 #define HB_LANES 16
 #define HB_V 4
 
-static inline float term(int metric, float a, float b) {
+static inline float term(int metric, double mp, float a, float b) {
     const float t = a - b;
+    if (metric == 4) return (float)pow((double)fabsf(t), mp);
     return metric == 1 ? fabsf(t) : sqrtf(fabsf(t));
 }
 
-static float dist_metric(const float *a, const float *b, int d, int metric) {
+static float dist_metric(const float *a, const float *b, int d, int metric, double mp) {
     float s[HB_LANES];
     for (int l = 0; l < HB_LANES; l++) s[l] = 0.0f;
     for (int c = 0; c < d; c += HB_LANES * HB_V)
@@ -84,7 +88,7 @@ static float dist_metric(const float *a, const float *b, int d, int metric) {
                     const float t = a[j] - b[j];
                     s[l] = fmaf(t, t, s[l]);
                 } else {
-                    s[l] = s[l] + term(metric, a[j], b[j]);
+                    s[l] = s[l] + term(metric, mp, a[j], b[j]);
                 }
             }
     for (int o = HB_LANES / 2; o >= 1; o >>= 1)
@@ -94,7 +98,9 @@ static float dist_metric(const float *a, const float *b, int d, int metric) {
 
 static inline const float *vec(const hb_t *g, int32_t v) { return g->base + (int64_t)v * g->d; }
 
-static inline float dist(const hb_t *g, const float *a, const float *b) { return dist_metric(a, b, g->d, g->metric); }
+static inline float dist(const hb_t *g, const float *a, const float *b) {
+    return dist_metric(a, b, g->d, g->metric, g->mp);
+}
 
 static inline int32_t *nbrs(const hb_t *g, int32_t v, int l, int *cnt) {
     if (l == 0) {
@@ -337,13 +343,15 @@ static uint64_t splitmix64(uint64_t x) {
 }
 
 /* ----------------------------------------------------------- public API */
-void *hb_build(const float *base, int64_t n, int d, int metric, int M, int efc, uint64_t seed, int nthreads,
-               int verbose, int batch_max) {
-    if (n < 1 || d < 1 || metric < 1 || metric > 3 || M < 2 || M > 127 || efc < 1 || batch_max < 1) return NULL;
+void *hb_build(const float *base, int64_t n, int d, int metric, double mp, int M, int efc, uint64_t seed,
+               int nthreads, int verbose, int batch_max) {
+    if (n < 1 || d < 1 || metric < 1 || metric > 4 || M < 2 || M > 127 || efc < 1 || batch_max < 1) return NULL;
+    if (metric == 4 && !(mp > 0.0 && mp <= 2.0)) return NULL;
     hb_t *g = (hb_t *)calloc(1, sizeof(hb_t));
     g->n = n;
     g->d = d;
     g->metric = metric;
+    g->mp = mp;
     g->M = M;
     g->M0 = 2 * M;
     g->efc = efc;

@@ -1,7 +1,7 @@
 """The per-p HNSW baseline (the U-HNSW paper's Sec. 4.3, Fig. 4) on the GPU:
-a graph G_p built for one p (uhnsw_build_graph, metric 4) and walked under
-sum |x - q|^p (v_log / v_exp), against the oracle walking the same graph
-under the same key with FP64 terms.
+a graph G_p built for one p (the input generator's CPU builder, metric 4)
+and walked under sum |x - q|^p (v_log / v_exp), against the oracle walking
+the same graph under the same key with FP64 terms.
 
 Parity rule for this walk: its keys are transcendental, so the GPU's FP32
 keys and the oracle's differ in the last bits and the two walks may take a
@@ -15,6 +15,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 import oracle  # noqa: E402
+import synth.graphs as sg  # noqa: E402
 from parity import check_row, lp_sums64  # noqa: E402
 from test_gpu_parity import _say, run_device  # noqa: E402
 
@@ -32,9 +33,9 @@ def test_pgraph_walk_parity(torch_cuda, wl1, p0):
     from paper_2605_02030_amd import uhnsw
 
     wl, _, g2 = wl1
+    gp = sg.build_graph(wl.base, sg.METRIC_LP, M=16, ef_construction=200, seed=5, cache=False, metric_p=p0)
     ctx = uhnsw.Context(0)
     try:
-        gp = uhnsw.build_graph(ctx, wl.base, uhnsw.METRIC_LP, M=16, ef_construction=200, seed=5, metric_p=p0)
         ctx.load_graphs(wl.base, gp, g2, variant=uhnsw.VARIANT_PGRAPH, graph_p=p0)
         g, v = ctx.layout()
         p = np.full(wl.nq, p0, np.float32)

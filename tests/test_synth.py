@@ -121,3 +121,25 @@ def test_extended_workloads_share_vectors():
     d = synth.make_workload(2, n=2000)
     assert np.array_equal(c.base, d.base) and np.array_equal(c.queries, d.queries)
     np.testing.assert_array_equal(np.unique(c.p), synth.P_GRID_EXT)
+
+
+def test_builder_fixed_p_metric():
+    """Metric 4 (sum |x - y|^p, a graph built for one p): at p = 1 every term
+    is |x - y| exactly, so the graph equals the L1 graph edge for edge; at
+    p = 0.7 it is a valid HNSW graph; p outside (0, 2] is refused."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    base = rng.standard_normal((2000, 12)).astype(np.float32)
+    a = sg.build_graph(base, sg.METRIC_L1, M=8, ef_construction=40, seed=3, cache=False)
+    b = sg.build_graph(base, sg.METRIC_LP, M=8, ef_construction=40, seed=3, cache=False, metric_p=1.0)
+    assert a.entry == b.entry and a.max_level == b.max_level
+    for la, lb in zip(a.layers, b.layers):
+        np.testing.assert_array_equal(la.row_ptr, lb.row_ptr)
+        np.testing.assert_array_equal(la.col, lb.col)
+    c = sg.build_graph(base, sg.METRIC_LP, M=8, ef_construction=40, seed=3, cache=False, metric_p=0.7)
+    np.testing.assert_array_equal(c.levels, a.levels)  # the level draw does not depend on the metric
+    assert any(not np.array_equal(x.col, y.col) for x, y in zip(a.layers, c.layers))
+    for L in c.layers:
+        assert np.diff(L.row_ptr).max() <= 16
+    for bad in (0.0, -1.0, 2.5):
+        with pytest.raises(ValueError):
+            sg.build_graph(base, sg.METRIC_LP, M=8, ef_construction=40, seed=3, cache=False, metric_p=bad)
