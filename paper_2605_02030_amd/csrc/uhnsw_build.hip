@@ -145,13 +145,12 @@ __device__ int search_layer(const BuildArgs &A, const BLds &L, const float (&qv)
         const int32_t *row = layer_row(A, (int32_t)node, l, &width);
         const int32_t nb = lane < width ? row[lane] : -1;
         bool fresh = false;
-        uint32_t vs = 0, vt = 0;
         if (nb >= 0) {
+            uint32_t vs, vt;
             L.vis.locate(nb, vs, vt);
-            fresh = !L.vis.seen(vs, vt);
+            fresh = L.vis.test_and_mark(vs, vt);
         }
         wave_sync();
-        if (fresh) L.vis.mark(vs, vt);
         const uint64_t fm = ballot(fresh);
         const int nnew = popc64(fm);
         if (nnew == 0) continue;
@@ -457,7 +456,7 @@ int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, i
         int kb = 1;
         while (kb < 31 && ((int64_t)1 << kb) < n) ++kb;
         if (kb < vis_bits + 1) kb = vis_bits + 1;
-        vis_kbits = (kb - vis_bits <= 15) ? kb : 0;
+        vis_kbits = vis_tags_fit(kb, vis_bits) ? kb : 0;
         if (build_lds_bytes(ef_cap, vis_bits, vis_kbits) <= 24 * 1024) break;
     }
     if (vis_bits < 10) return build_fail(UHNSW_EUNSUPPORTED, "ef_construction too large for the LDS plan");

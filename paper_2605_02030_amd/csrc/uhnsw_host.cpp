@@ -300,7 +300,7 @@ int make_plan(uhnsw_ctx *c, int k_max, int ef_max, const uhnsw_params &prm, Plan
         while (kb < 31 && ((int64_t)1 << kb) < c->n) ++kb;
         if (kb < b + 1) kb = b + 1;
         *bits = b;
-        *kbits = (kb - b <= 15) ? kb : 0;
+        *kbits = vis_tags_fit(kb, b) ? kb : 0;
     };
     int slots = prm.visited_slots;
     if (slots <= 0 && ef_max > 512) {

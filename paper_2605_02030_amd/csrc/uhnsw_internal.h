@@ -10,6 +10,12 @@ namespace uhnsw {
 constexpr int kWave = 64;
 constexpr int kUCap = 64;            // neighbours gathered per walk step (beam_width * M0)
 constexpr uint32_t kExpBit = 0x80000000u;
+// Visited cache: 16-bit tags in sets of kVisWays (8). With 2^bits tags and
+// ids below 2^kbits a tag needs kbits - bits + kVisWayBits bits, plus one for
+// "empty", within 16.
+constexpr int kVisWayBits = 3;
+constexpr int kVisWays = 1 << kVisWayBits;
+inline constexpr bool vis_tags_fit(int kbits, int bits) { return kbits - bits + kVisWayBits <= 15; }
 constexpr uint32_t kIdMask = 0x7fffffffu;
 
 // Row layout of one stored vector: element j is read by lane (j / V) % G of
