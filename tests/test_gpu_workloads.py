@@ -4,8 +4,9 @@
   the launch configurations bench.py times, compared with the oracle on 527
   sampled queries; recall@10 against the stored FP64 ground truth.
 * The precision form (d = 960 gamma features; BF16 and FP16 walk storage,
-  FP32 re-rank) and the batching form (d = 100 unit vectors, K in {1, 10,
-  100}, ef in [K, 512]) at reduced n with the full dimension.
+  FP32 re-rank), the batching form (d = 100 unit vectors, K in {1, 10,
+  100}, ef in [K, 512]) and the serving form (d = 96 unit vectors, FP16 walk,
+  K in {10, 100}) at reduced n with the full dimension.
 """
 import os
 import sys
@@ -244,6 +245,47 @@ def test_batching_form_d100_mixed(torch_cuda, wl4_small):
     for a, b in zip(gpu[:2], plain[:2]):
         np.testing.assert_array_equal(a, b)
     G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base)
+    compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v)
+
+
+@pytest.fixture(scope="module")
+def wl5_small():
+    wl = synth.make_workload(5, n=30_000, nq=200)
+    g1, g2 = sg.build_graphs(wl, cache=False)
+    return wl, g1, g2
+
+
+def test_serving_form_d96_fp16(torch_cuda, wl5_small):
+    """The serving workload's shape at reduced n: d = 96 unit vectors (pitch
+    padded to 128), FP16 walk with FP32 re-rank, K in {10, 100}, ef =
+    max(K, 128). One fused launch and the same queries served as a Poisson
+    mix at 100k/s: identical to each other, and C equal to the oracle walking
+    the same FP16 storage, top-K by the near-tie rule."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl5_small
+    ctx = uhnsw.Context(0)
+    try:
+        ctx.load_graphs(wl.base, g1, g2, storage=uhnsw.STORE_F16)
+        g, v = ctx.layout()
+        assert (g, v) == (8, 4)
+        gpu = run_device(torch_cuda, ctx, wl.queries, wl.p, wl.k, wl.ef, 100, 128,
+                         params=uhnsw.default_params(fused=1))
+        srv = uhnsw.Server(ctx, k_max=100, ef_max=128)
+        try:
+            rng = np.random.Generator(np.random.PCG64(55))
+            arrival = np.cumsum(rng.exponential(1e6 / 100_000, wl.nq))
+            ids, dists, status, *_ = srv.drive(wl.queries, wl.p, wl.k, wl.ef, arrival)
+        finally:
+            srv.stop()
+    finally:
+        ctx.close()
+    assert (status == 0).all()
+    for i in range(wl.nq):
+        K = int(wl.k[i])
+        np.testing.assert_array_equal(ids[i, :K], gpu[0][i, :K])
+        np.testing.assert_array_equal(dists[i, :K], gpu[1][i, :K])
+    G1, G2, D = oracle.Graph(g1), oracle.Graph(g2), oracle.Data(wl.base, storage=oracle.F16)
     compare(wl.base, G1, G2, D, wl.queries, wl.p, wl.k, wl.ef, gpu, g, v)
 
 
