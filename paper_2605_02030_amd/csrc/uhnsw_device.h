@@ -1269,15 +1269,19 @@ __device__ __forceinline__ void verify_call(const SearchArgs &A, int64_t qi, cha
 
 // Occupancy target of the fused kernel and VGPRs given to row data in flight.
 // Rows of up to 256 dimensions (G <= 16 lanes per row): 5 waves per SIMD
-// (<= 96 VGPRs) with 32 VGPRs of row data, for every storage type; the
+// (<= 96 VGPRs) with 24 VGPRs of row data, for every storage type; the
 // verification state makes this kernel larger than the walk, and the extra
-// waves pay for the smaller row batches (measured on the 1M x 128 workload).
+// waves pay for the smaller row batches. Measured on the 1M x 128 workload
+// (beam 2, 2,048 visited slots): 24 VGPRs (three 8-row steps of 16-bit rows,
+// one of FP32 rows) against 32 cut the BF16 launch from 2.37 to 2.28 ms and
+// the FP32 one from 3.75 to 3.67 ms (fewer spills in the merge); 16 VGPRs
+// give 2.37 ms, and a fourth wave per SIMD with 32 VGPRs 2.65 ms.
 // Longer rows (one row per 32 or 64 lanes) keep four rows in flight instead:
 // 3 waves with FP32 rows, 4 with 16-bit rows (measured at d = 960).
 template <typename T, int G>
 constexpr int fused_waves_per_eu() { return G <= 16 ? 5 : (sizeof(T) == 4 ? 3 : 4); }
 template <typename T, int G>
-constexpr int fused_rb_vgprs() { return G <= 16 ? 32 : (sizeof(T) == 4 ? 64 : 32); }
+constexpr int fused_rb_vgprs() { return G <= 16 ? 24 : (sizeof(T) == 4 ? 64 : 32); }
 
 // BEAM (1 or 2, equal to A.beam) specialises the fused kernel.
 template <int G, int NCH, typename T, int BEAM, bool EXT>
