@@ -116,6 +116,27 @@ def test_full_size_bench_configurations(torch_cuda, wl2_full, form):
     assert rec >= 0.9
 
 
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("slots,fused,beam", [(64, 0, 1), (128, 1, 2)])
+def test_full_size_id_slot_cache(torch_cuda, wl2_full, slots, fused, beam):
+    """Visited caches too small for 16-bit tags at a million ids: with 64
+    slots a tag would need 20 - 6 + 3 = 17 bits, with 128 slots 16, so the
+    cache holds 32-bit ids instead. A cache only decides which rows are
+    gathered again, never which nodes enter W, so C and R still equal the
+    oracle's (527 sampled queries; the walk gathers more rows)."""
+    from paper_2605_02030_amd import uhnsw
+
+    wl, g1, g2 = wl2_full
+    sample = np.arange(7, wl.nq, SAMPLE_STEP)
+    prm = uhnsw.default_params(visited_slots=slots, fused=fused, beam_width=beam)
+    ctx = uhnsw.Context(0)
+    try:
+        ctx.load_graphs(wl.base, g1, g2)
+        _sample_compare(torch_cuda, ctx, wl, g1, g2, 128, prm, uhnsw.STORE_F32, sample, w=beam)
+    finally:
+        ctx.close()
+
+
 @pytest.fixture(scope="module")
 def wl7_full():
     _say("workload 7 full size (extended index): generating inputs and graphs (cached when present)")
