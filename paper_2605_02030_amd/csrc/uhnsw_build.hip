@@ -32,6 +32,7 @@
 #include <vector>
 
 #include "uhnsw_device.h"
+#include "uhnsw_guard.h"
 
 namespace uhnsw {
 namespace {
@@ -400,9 +401,9 @@ struct uhnsw_built_graph {
 
 extern "C" {
 
-int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, float metric_p,
-                      int32_t M, int32_t ef_construction, uint64_t seed, int32_t batch_max,
-                      uhnsw_built_graph **out) {
+static int build_graph_body(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, float metric_p,
+                            int32_t M, int32_t ef_construction, uint64_t seed, int32_t batch_max,
+                            uhnsw_built_graph **out) {
     if (!ctx) return UHNSW_EINVAL;
     auto build_fail = [ctx](int code, const std::string &msg) {
         ctx_set_error(ctx, ("uhnsw_build_graph: " + msg).c_str());
@@ -630,6 +631,15 @@ int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, i
     G->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = G.release();
     return UHNSW_OK;
+}
+
+int uhnsw_build_graph(uhnsw_ctx *ctx, const float *base, int64_t n, int32_t d, int32_t metric, float metric_p,
+                      int32_t M, int32_t ef_construction, uint64_t seed, int32_t batch_max,
+                      uhnsw_built_graph **out) {
+    const auto body = [&] {
+        return build_graph_body(ctx, base, n, d, metric, metric_p, M, ef_construction, seed, batch_max, out);
+    };
+    return no_throw("uhnsw_build_graph", body, [&](const char *w) { if (ctx) ctx_set_error(ctx, w); });
 }
 
 int uhnsw_built_graph_view(const uhnsw_built_graph *g, uhnsw_graph *out, double *build_seconds,

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "uhnsw.h"
+#include "uhnsw_guard.h"
 #include "uhnsw_internal.h"
 
 using namespace uhnsw;
@@ -567,7 +568,7 @@ void uhnsw_default_params(uhnsw_params *p) {
     p->persistent = 3;  // cost-ordered launch: same results, shorter tail
 }
 
-int uhnsw_create(int device, uhnsw_ctx **out) {
+static int create_body(int device, uhnsw_ctx **out) {
     if (!out) {
         g_create_error = "out is NULL";
         return UHNSW_EINVAL;
@@ -597,6 +598,11 @@ int uhnsw_create(int device, uhnsw_ctx **out) {
     }
     *out = c;
     return UHNSW_OK;
+}
+
+int uhnsw_create(int device, uhnsw_ctx **out) {
+    const auto body = [&] { return create_body(device, out); };
+    return no_throw("uhnsw_create", body, [&](const char *w) { g_create_error = w; });
 }
 
 void uhnsw_destroy(uhnsw_ctx *c) {
@@ -637,7 +643,7 @@ void uhnsw_destroy(uhnsw_ctx *c) {
 
 const char *uhnsw_last_error(const uhnsw_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
-int uhnsw_reset(uhnsw_ctx *c) {
+static int reset_body(uhnsw_ctx *c) {
     if (!c) return UHNSW_EINVAL;
     if (c->servers.load() > 0) return fail(c, UHNSW_ESTATE, "uhnsw_reset refused: a server is running");
     hipError_t e = hipSetDevice(c->device);
@@ -669,7 +675,12 @@ int uhnsw_reset(uhnsw_ctx *c) {
     return UHNSW_OK;
 }
 
-int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
+int uhnsw_reset(uhnsw_ctx *c) {
+    const auto body = [&] { return reset_body(c); };
+    return no_throw("uhnsw_reset", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int load_graphs_body(uhnsw_ctx *c, const uhnsw_index *idx) {
     if (!c) return UHNSW_EINVAL;
     int r0 = check_index(&c->err, idx);
     if (r0) return r0;
@@ -732,26 +743,54 @@ int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
     return UHNSW_OK;
 }
 
-int uhnsw_load_graph_files(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
-                           int32_t storage, int32_t variant) {
+int uhnsw_load_graphs(uhnsw_ctx *c, const uhnsw_index *idx) {
+    const auto body = [&] { return load_graphs_body(c, idx); };
+    return no_throw("uhnsw_load_graphs", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int load_graph_files_body(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
+                                 int32_t storage, int32_t variant) {
     if (!c) return UHNSW_EINVAL;
     IndexFiles f;
     int r = read_index_files(&c->err, vec_path, g1_path, g2_path, storage, variant, &f);
     return r ? r : uhnsw_load_graphs(c, &f.idx);
 }
 
-int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len) {
+int uhnsw_load_graph_files(uhnsw_ctx *c, const char *vec_path, const char *g1_path, const char *g2_path,
+                           int32_t storage, int32_t variant) {
+    const auto body = [&] { return load_graph_files_body(c, vec_path, g1_path, g2_path, storage, variant); };
+    return no_throw("uhnsw_load_graph_files", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int check_index_body(const uhnsw_index *idx, char *msg, int32_t msg_len) {
     std::string err;
     return check_result(err, check_index(&err, idx), msg, msg_len);
 }
 
-int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
-                            int32_t variant, char *msg, int32_t msg_len) {
+int uhnsw_check_index(const uhnsw_index *idx, char *msg, int32_t msg_len) {
+    const auto body = [&] { return check_index_body(idx, msg, msg_len); };
+    return no_throw("uhnsw_check_index", body, [&](const char *w) {
+        if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", w);
+    });
+}
+
+static int check_index_files_body(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
+                                  int32_t variant, char *msg, int32_t msg_len) {
     std::string err;
     IndexFiles f;
     int r = read_index_files(&err, vec_path, g1_path, g2_path, storage, variant, &f);
     if (!r) r = check_index(&err, &f.idx);
     return check_result(err, r, msg, msg_len);
+}
+
+int uhnsw_check_index_files(const char *vec_path, const char *g1_path, const char *g2_path, int32_t storage,
+                            int32_t variant, char *msg, int32_t msg_len) {
+    const auto body = [&] {
+        return check_index_files_body(vec_path, g1_path, g2_path, storage, variant, msg, msg_len);
+    };
+    return no_throw("uhnsw_check_index_files", body, [&](const char *w) {
+        if (msg && msg_len > 0) std::snprintf(msg, (size_t)msg_len, "%s", w);
+    });
 }
 
 int uhnsw_get_layout(const uhnsw_ctx *c, int32_t *g, int32_t *v) {
@@ -1111,10 +1150,10 @@ static int stream_set(uhnsw_ctx *c, hipStream_t st, uhnsw_ctx::StreamSet **out) 
     return UHNSW_OK;
 }
 
-int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
-                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
-                        float *cand_keys, int32_t c_stride, void *stream) {
+static int search_device_body(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                              const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                              int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                              float *cand_keys, int32_t c_stride, void *stream) {
     if (!c) return UHNSW_EINVAL;
     if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
     uhnsw_ctx::StreamSet *S = nullptr;
@@ -1124,17 +1163,39 @@ int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const fl
                      cand_keys, c_stride, stream);
 }
 
-int uhnsw_search_device_noalloc(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                                const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
-                                int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats,
-                                int32_t *cand_ids, float *cand_keys, int32_t c_stride, void *stream) {
+int uhnsw_search_device(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                        const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                        int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats, int32_t *cand_ids,
+                        float *cand_keys, int32_t c_stride, void *stream) {
+    const auto body = [&] {
+        return search_device_body(c, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists, stats,
+                                  cand_ids, cand_keys, c_stride, stream);
+    };
+    return no_throw("uhnsw_search_device", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int search_device_noalloc_body(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                                      const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                                      int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats,
+                                      int32_t *cand_ids, float *cand_keys, int32_t c_stride, void *stream) {
     if (!c) return UHNSW_EINVAL;
     if (!c->noalloc) return fail(c, UHNSW_ESTATE, "no fixed scratch region on device %d", c->device);
     return search_on(c, nullptr, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists, stats,
                      cand_ids, cand_keys, c_stride, stream, c->noalloc, kNoAllocScratchBytes);
 }
 
-int uhnsw_probe_gather(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {
+int uhnsw_search_device_noalloc(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                                const int32_t *ef, int32_t k_max, int32_t ef_max, const uhnsw_params *prm_in,
+                                int32_t k_stride, int64_t *ids, float *dists, uhnsw_stats *stats,
+                                int32_t *cand_ids, float *cand_keys, int32_t c_stride, void *stream) {
+    const auto body = [&] {
+        return search_device_noalloc_body(c, queries, nq, p, k, ef, k_max, ef_max, prm_in, k_stride, ids, dists,
+                                          stats, cand_ids, cand_keys, c_stride, stream);
+    };
+    return no_throw("uhnsw_search_device_noalloc", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int probe_gather_body(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {
     if (!c || !gbs) return UHNSW_EINVAL;
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
     if (row_bytes != 128 && row_bytes != 256 && row_bytes != 512)
@@ -1172,7 +1233,12 @@ int uhnsw_probe_gather(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {
     return UHNSW_OK;
 }
 
-int uhnsw_probe_transcendental(uhnsw_ctx *c, double *ops_per_s) {
+int uhnsw_probe_gather(uhnsw_ctx *c, int32_t row_bytes, double *gbs) {
+    const auto body = [&] { return probe_gather_body(c, row_bytes, gbs); };
+    return no_throw("uhnsw_probe_gather", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int probe_transcendental_body(uhnsw_ctx *c, double *ops_per_s) {
     if (!c || !ops_per_s) return UHNSW_EINVAL;
     HIP_OR_FAIL(c, hipSetDevice(c->device));
     DevBuf sink;
@@ -1201,15 +1267,20 @@ int uhnsw_probe_transcendental(uhnsw_ctx *c, double *ops_per_s) {
     return UHNSW_OK;
 }
 
+int uhnsw_probe_transcendental(uhnsw_ctx *c, double *ops_per_s) {
+    const auto body = [&] { return probe_transcendental_body(c, ops_per_s); };
+    return no_throw("uhnsw_probe_transcendental", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
 int uhnsw_graph_captures(const uhnsw_ctx *c, int64_t *count) {
     if (!c || !count) return UHNSW_EINVAL;
     *count = c->graph_captures;
     return UHNSW_OK;
 }
 
-int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t flags, uhnsw_params *prm,
-                   void *stream) {
+static int autotune_body(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                         const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t flags, uhnsw_params *prm,
+                         void *stream) {
     if (!c || !prm) return UHNSW_EINVAL;
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
     if (nq < 1) return fail(c, UHNSW_EINVAL, "autotune needs queries");
@@ -1335,9 +1406,16 @@ int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *
     return UHNSW_OK;
 }
 
-int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
-                 const int32_t *ef, const uhnsw_params *prm_in, int32_t k_stride, int64_t *ids, float *dists,
-                 uhnsw_stats *stats) {
+int uhnsw_autotune(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                   const int32_t *ef, int32_t k_max, int32_t ef_max, int32_t flags, uhnsw_params *prm,
+                   void *stream) {
+    const auto body = [&] { return autotune_body(c, queries, nq, p, k, ef, k_max, ef_max, flags, prm, stream); };
+    return no_throw("uhnsw_autotune", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
+}
+
+static int search_body(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                       const int32_t *ef, const uhnsw_params *prm_in, int32_t k_stride, int64_t *ids, float *dists,
+                       uhnsw_stats *stats) {
     if (!c) return UHNSW_EINVAL;
     if (c->failed) return fail(c, UHNSW_ESTATE, "context failed earlier: %s", c->err.c_str());
     if (!c->loaded) return fail(c, UHNSW_ESTATE, "no index loaded");
@@ -1464,6 +1542,13 @@ int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p,
     std::memcpy(dists, host[5], bytes[5]);
     if (stats) std::memcpy(stats, host[6], bytes[6]);
     return UHNSW_OK;
+}
+
+int uhnsw_search(uhnsw_ctx *c, const float *queries, int64_t nq, const float *p, const int32_t *k,
+                 const int32_t *ef, const uhnsw_params *prm_in, int32_t k_stride, int64_t *ids, float *dists,
+                 uhnsw_stats *stats) {
+    const auto body = [&] { return search_body(c, queries, nq, p, k, ef, prm_in, k_stride, ids, dists, stats); };
+    return no_throw("uhnsw_search", body, [&](const char *w) { if (c) ctx_set_error(c, w); });
 }
 
 }  // extern "C"

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "uhnsw.h"
+#include "uhnsw_guard.h"
 #include "uhnsw_internal.h"
 
 namespace {
@@ -232,9 +233,28 @@ bool launch_pending(uhnsw_server *S) {
     return true;
 }
 
+void dispatch_loop(uhnsw_server *S, std::unique_lock<std::mutex> &lk);
+
+// The server's thread. A C++ exception in its loop (a result queue that
+// cannot grow) stops dispatching and is reported as UHNSW_ENOMEM by the
+// next submit or poll; batches already launched are synchronised by stop.
 void dispatcher(uhnsw_server *S) {
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
+    try {
+        dispatch_loop(S, lk);
+    } catch (const std::exception &e) {
+        S->error = UHNSW_ENOMEM;
+        try {
+            S->err = std::string("serving dispatcher: ") + e.what();
+        } catch (...) {
+        }
+    } catch (...) {
+        S->error = UHNSW_ENOMEM;
+    }
+}
+
+void dispatch_loop(uhnsw_server *S, std::unique_lock<std::mutex> &lk) {
     for (;;) {
         bool any_busy = false;
         for (auto &l : S->lanes) any_busy |= l.busy;
@@ -275,7 +295,7 @@ void uhnsw_serve_default_config(uhnsw_serve_config *c) {
     uhnsw_default_params(&c->params);
 }
 
-int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out) {
+static int serve_start_body(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out) {
     if (!ctx || !cfg || !out) return UHNSW_EINVAL;
     *out = nullptr;
     int32_t g, v;
@@ -328,25 +348,41 @@ int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_serve
     }
     S->max_batch = B;
     S->slots_total = slots;
-    S->slot_q.assign((size_t)slots * S->d, 0.f);
-    S->slot.resize(slots);
-    for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
-    S->lanes.resize(streams);
-    (void)hipSetDevice(S->device);
-    for (auto &L : S->lanes)
-        if (alloc_lane(L, B, S->d, cfg->k_max) != hipSuccess) {
-            for (auto &l : S->lanes) free_lane(l);
-            delete S;
-            return UHNSW_ENOMEM;
+    try {  // host containers and the dispatcher thread; on failure nothing is kept
+        S->slot_q.assign((size_t)slots * S->d, 0.f);
+        S->slot.resize(slots);
+        for (int i = slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+        S->lanes.resize(streams);
+        (void)hipSetDevice(S->device);
+        for (auto &L : S->lanes)
+            if (alloc_lane(L, B, S->d, cfg->k_max) != hipSuccess) {
+                for (auto &l : S->lanes) free_lane(l);
+                delete S;
+                return UHNSW_ENOMEM;
+            }
+        S->t0 = std::chrono::steady_clock::now();
+        uhnsw::ctx_servers(ctx, +1);  // the index may not be replaced while this server runs
+        try {
+            S->th = std::thread(dispatcher, S);
+        } catch (...) {
+            uhnsw::ctx_servers(ctx, -1);
+            throw;
         }
-    S->t0 = std::chrono::steady_clock::now();
-    uhnsw::ctx_servers(ctx, +1);  // the index may not be replaced while this server runs
-    S->th = std::thread(dispatcher, S);
+    } catch (...) {
+        for (auto &l : S->lanes) free_lane(l);
+        delete S;
+        throw;
+    }
     *out = S;
     return UHNSW_OK;
 }
 
-int uhnsw_serve_submit(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
+int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out) {
+    const auto body = [&] { return serve_start_body(ctx, cfg, out); };
+    return uhnsw::no_throw("uhnsw_serve_start", body, [&](const char *w) { if (ctx) uhnsw::ctx_set_error(ctx, w); });
+}
+
+static int serve_submit_body(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
     if (!S || !q) return UHNSW_EINVAL;
     if (!uhnsw::p_in_range(S->variant, p) || k < 1 || k > S->cfg.k_max || ef < k || ef > S->cfg.ef_max)
         return UHNSW_EINVAL;
@@ -368,7 +404,12 @@ int uhnsw_serve_submit(uhnsw_server *S, const float *q, float p, int32_t k, int3
     return UHNSW_OK;
 }
 
-int uhnsw_serve_poll(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int32_t *n_out) {
+int uhnsw_serve_submit(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
+    const auto body = [&] { return serve_submit_body(S, q, p, k, ef, tag); };
+    return uhnsw::no_throw("uhnsw_serve_submit", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
+}
+
+static int serve_poll_body(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int32_t *n_out) {
     if (!S || !n_out || (max > 0 && !out)) return UHNSW_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     int n = 0;
@@ -379,6 +420,11 @@ int uhnsw_serve_poll(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int3
     *n_out = n;
     const int e = S->error.load();
     return e ? e : UHNSW_OK;
+}
+
+int uhnsw_serve_poll(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int32_t *n_out) {
+    const auto body = [&] { return serve_poll_body(S, out, max, n_out); };
+    return uhnsw::no_throw("uhnsw_serve_poll", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
 }
 
 int uhnsw_serve_info(uhnsw_server *S, int64_t *info) {
@@ -412,9 +458,9 @@ int uhnsw_serve_stop(uhnsw_server *S) {
     return rc;
 }
 
-int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const int32_t *qidx, const float *p,
-                      const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
-                      float *dists, uhnsw_stats *stats, double *times, int32_t *status) {
+static int serve_drive_body(uhnsw_server *S, int64_t n, const float *queries, const int32_t *qidx, const float *p,
+                            const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
+                            float *dists, uhnsw_stats *stats, double *times, int32_t *status) {
     if (!S || n < 0 || out_k < 1 || out_k > UHNSW_KMAX ||
         (n > 0 && (!queries || !p || !k || !ef || !arrival_us || !ids || !dists || !times || !status)))
         return UHNSW_EINVAL;
@@ -451,6 +497,15 @@ int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const in
         if (m == 0) std::this_thread::yield();
     }
     return UHNSW_OK;
+}
+
+int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const int32_t *qidx, const float *p,
+                      const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
+                      float *dists, uhnsw_stats *stats, double *times, int32_t *status) {
+    const auto body = [&] {
+        return serve_drive_body(S, n, queries, qidx, p, k, ef, arrival_us, out_k, ids, dists, stats, times, status);
+    };
+    return uhnsw::no_throw("uhnsw_serve_drive", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
 }
 
 }  // extern "C"

@@ -208,3 +208,34 @@ def _write(path, data):
     with open(path, "wb") as f:
         f.write(data)
     return str(path)
+
+
+def test_host_allocation_failure_is_an_error_code(small, tmp_path):
+    """A host allocation that fails inside an entry point ends the call with
+    UHNSW_ENOMEM and a message: no C++ exception crosses the C boundary. A
+    child process caps its address space 1 GiB above what it already maps
+    and asks uhnsw_check_index_files to read a 4 GiB (sparse) vector file;
+    without the guard the child would end in std::terminate."""
+    import os
+    import subprocess
+    import sys
+
+    wl, g1, g2 = small
+    vp, p1, p2 = (str(tmp_path / f) for f in ("big.fbin", "g1.uhg", "g2.uhg"))
+    sg.save_graph_file(p1, g1)
+    sg.save_graph_file(p2, g2)
+    with open(vp, "wb") as f:
+        f.truncate(4 << 30)
+    child = f"""
+import resource
+from paper_2605_02030_amd import uhnsw
+vm = next(int(l.split()[1]) * 1024 for l in open('/proc/self/status') if l.startswith('VmSize:'))
+resource.setrlimit(resource.RLIMIT_AS, (vm + (1 << 30), resource.RLIM_INFINITY))
+rc, msg = uhnsw.check_index_files({vp!r}, {p1!r}, {p2!r})
+print(rc, msg)
+"""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", child], cwd=root, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rc, _, msg = r.stdout.strip().partition(" ")
+    assert int(rc) == -2 and msg.startswith("uhnsw_check_index_files: host resources exhausted"), r.stdout
