@@ -211,6 +211,60 @@ def check_index_files(vec_path: str, g1_path: str, g2_path: str, storage: int = 
     return rc, msg.value.decode()
 
 
+def _stream_handle(stream):
+    """A raw hipStream_t from a torch stream, an int, or None (torch's
+    current stream)."""
+    import torch
+
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _check_device_args(queries, p, k, ef, ids=None, dists=None, stats=None, cand_ids=None, cand_keys=None):
+    """The device entry points take raw pointers: refuse host tensors, wrong
+    dtypes, non-contiguous views and short outputs here (TypeError /
+    ValueError) rather than hand the kernels a pointer they would misread."""
+    import torch
+
+    def need(t, name, dtype, rows=None, words=None):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name}: a torch tensor is required")
+        if not t.is_cuda:
+            raise ValueError(f"{name}: must be a device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: must be contiguous")
+        if t.dtype != dtype:
+            raise TypeError(f"{name}: dtype {t.dtype}, expected {dtype}")
+        if rows is not None and (t.dim() < 1 or t.shape[0] < rows):
+            raise ValueError(f"{name}: {tuple(t.shape)} has fewer than {rows} rows")
+        if words is not None and t.numel() < words:
+            raise ValueError(f"{name}: {t.numel()} elements, at least {words} needed")
+
+    need(queries, "queries", torch.float32)
+    if queries.dim() != 2:
+        raise ValueError("queries: (nq, d) expected")
+    nq = queries.shape[0]
+    for t, name, dt in ((p, "p", torch.float32), (k, "k", torch.int32), (ef, "ef", torch.int32)):
+        need(t, name, dt, words=nq)
+    for t, name, dt in ((ids, "ids", torch.int64), (dists, "dists", torch.float32)):
+        if t is not None:
+            need(t, name, dt, rows=nq)
+            if t.dim() != 2:
+                raise ValueError(f"{name}: (nq, k_stride) expected")
+    if ids is not None and dists is not None and ids.shape[1] != dists.shape[1]:
+        raise ValueError("ids and dists: different k_stride")
+    if stats is not None:
+        need(stats, "stats", torch.int32, words=nq * STATS_WORDS)
+    if (cand_ids is None) != (cand_keys is None):
+        raise ValueError("cand_ids and cand_keys: give both or neither")
+    if cand_ids is not None:
+        need(cand_ids, "cand_ids", torch.int32, rows=nq)
+        need(cand_keys, "cand_keys", torch.float32, rows=nq)
+        if cand_ids.dim() != 2 or cand_ids.shape != cand_keys.shape:
+            raise ValueError("cand_ids / cand_keys: (nq, c_stride) each expected")
+
+
 class Context:
     """One libuhnsw context on one HIP device (owns the resident index)."""
 
@@ -277,17 +331,8 @@ class Context:
                       cand_ids=None, cand_keys=None, params: uhnsw_params | None = None, stream=None):
         """torch device tensors in and out; asynchronous on ``stream`` (torch
         stream or raw hipStream_t int; default: torch's current stream)."""
-        import torch
-
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        elif hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
-        for t in (queries, p, k, ef, ids, dists):
-            assert t.is_cuda and t.is_contiguous()
-        assert queries.dtype == torch.float32 and p.dtype == torch.float32
-        assert k.dtype == torch.int32 and ef.dtype == torch.int32
-        assert ids.dtype == torch.int64 and dists.dtype == torch.float32
+        _check_device_args(queries, p, k, ef, ids, dists, stats, cand_ids, cand_keys)
+        stream = _stream_handle(stream)
         nq = queries.shape[0]
         ks = ids.shape[1]
         cs = cand_ids.shape[1] if cand_ids is not None else 0
@@ -302,12 +347,8 @@ class Context:
                               cand_ids=None, cand_keys=None, params: uhnsw_params | None = None, stream=None):
         """search_device without any allocation (scratch from the device's
         fixed region; see include/uhnsw.h)."""
-        import torch
-
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        elif hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
+        _check_device_args(queries, p, k, ef, ids, dists, stats, cand_ids, cand_keys)
+        stream = _stream_handle(stream)
         cs = cand_ids.shape[1] if cand_ids is not None else 0
         prm = ctypes.byref(params) if params is not None else None
         self._check(uhnsw_search_device_noalloc(
@@ -321,12 +362,8 @@ class Context:
         """Time the execution knobs on these device tensors; returns tuned params.
         allow_beam: also choose the beam width (changes the walk); pipelined:
         time back-to-back launches with two in flight."""
-        import torch
-
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        elif hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
+        _check_device_args(queries, p, k, ef)
+        stream = _stream_handle(stream)
         flags = (UHNSW_TUNE_BEAM if allow_beam else 0) | (UHNSW_TUNE_PIPELINED if pipelined else 0)
         prm = params if params is not None else default_params()
         prm = uhnsw_params.from_buffer_copy(prm)

@@ -94,3 +94,50 @@ def test_null_arguments_rejected_without_device(lib):
     assert lib.uhnsw_reset(None) == lib.UHNSW_EINVAL
     assert lib.uhnsw_search(None, None, 0, None, None, None, None, 0, None, None, None) == lib.UHNSW_EINVAL
     lib.uhnsw_destroy(None)
+
+
+def test_device_arguments_checked_before_the_call(lib):
+    """The device entry points take raw pointers, so the binding refuses what
+    the kernels would misread -- host tensors, wrong dtypes, non-contiguous
+    views, short outputs, half of the candidate pair -- with TypeError /
+    ValueError, before any HIP call."""
+    import torch
+
+    nq, d = 4, 8
+    q, p = torch.zeros((nq, d)), torch.ones(nq)
+    k, ef = torch.full((nq,), 10, dtype=torch.int32), torch.full((nq,), 64, dtype=torch.int32)
+    with pytest.raises(ValueError, match="device tensor"):
+        lib._check_device_args(q, p, k, ef)
+    with pytest.raises(TypeError, match="torch tensor"):
+        lib._check_device_args(q.numpy(), p, k, ef)
+
+    # the checks after the device test, on host tensors made to report
+    # is_cuda (the checks read attributes only; nothing is launched)
+    had = "is_cuda" in torch.Tensor.__dict__
+    orig = torch.Tensor.__dict__.get("is_cuda")
+    try:
+        torch.Tensor.is_cuda = property(lambda self: True)
+        ok = dict(ids=torch.zeros((nq, 10), dtype=torch.int64), dists=torch.zeros((nq, 10)),
+                  stats=torch.zeros((nq, lib.STATS_WORDS), dtype=torch.int32))
+        lib._check_device_args(q, p, k, ef, **ok)
+        bad = [
+            (dict(k=k.long()), TypeError, "k: dtype"),
+            (dict(p=p.double()), TypeError, "p: dtype"),
+            (dict(q=q.t()), ValueError, "queries: must be contiguous"),
+            (dict(ef=ef[:2]), ValueError, "ef: 2 elements"),
+            (dict(ids=ok["ids"][:2]), ValueError, "ids: .* fewer than 4 rows"),
+            (dict(dists=torch.zeros((nq, 5))), ValueError, "different k_stride"),
+            (dict(stats=torch.zeros((nq, 2), dtype=torch.int32)), ValueError, "stats"),
+            (dict(cand_ids=torch.zeros((nq, 60), dtype=torch.int32)), ValueError, "both or neither"),
+        ]
+        for change, exc, msg in bad:
+            args = dict(q=q, p=p, k=k, ef=ef, **ok)
+            args.update(change)
+            with pytest.raises(exc, match=msg):
+                lib._check_device_args(args.pop("q"), args.pop("p"), args.pop("k"), args.pop("ef"), **args)
+    finally:
+        if had:
+            torch.Tensor.is_cuda = orig
+        else:
+            del torch.Tensor.is_cuda
+    assert not torch.zeros(1).is_cuda

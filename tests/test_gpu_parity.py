@@ -263,6 +263,34 @@ def test_host_api_rejects(torch_cuda, ctx1, wl1):
     assert ids.shape[0] == 0
 
 
+def test_device_api_rejects_bad_tensors(torch_cuda, ctx1, wl1):
+    """search_device and its allocation-free twin refuse, before any launch,
+    a host tensor, a wrong dtype or a short output (the binding checks what
+    the raw pointers would hide); a valid call afterwards still works."""
+    from paper_2605_02030_amd import uhnsw
+
+    torch = torch_cuda
+    wl, _, _ = wl1
+    dev = torch.device("cuda:0")
+    nq = 8
+    q = torch.from_numpy(np.ascontiguousarray(wl.queries[:nq])).to(dev)
+    p = torch.from_numpy(np.ascontiguousarray(wl.p[:nq])).to(dev)
+    k = torch.full((nq,), 10, dtype=torch.int32, device=dev)
+    ef = torch.full((nq,), 64, dtype=torch.int32, device=dev)
+    ids = torch.empty((nq, 10), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, 10), dtype=torch.float32, device=dev)
+    for call in (ctx1.search_device, ctx1.search_device_noalloc):
+        with pytest.raises(ValueError, match="device tensor"):
+            call(q.cpu(), p, k, ef, 10, 64, ids, dists)
+        with pytest.raises(TypeError, match="k: dtype"):
+            call(q, p, k.long(), ef, 10, 64, ids, dists)
+        with pytest.raises(ValueError, match="fewer than"):
+            call(q, p, k, ef, 10, 64, ids[:4], dists[:4])
+        call(q, p, k, ef, 10, 64, ids, dists)
+        torch.cuda.synchronize()
+        assert (ids.cpu().numpy() >= 0).all()
+
+
 def test_tiny_index_pads(torch_cuda):
     """n = 3: |C| < K; rows are padded with -1 / +inf."""
     from paper_2605_02030_amd import uhnsw
