@@ -478,7 +478,10 @@ int uhnsw_serve_drive(uhnsw_server *srv, int64_t n, const float *queries, const 
                       const int32_t *k, const int32_t *ef, const double *arrival_us, int32_t out_k, int64_t *ids,
                       float *dists, uhnsw_stats *stats, double *times, int32_t *status);
 
-/* Finish in-flight work, stop the dispatcher, free the server. */
+/* Finish in-flight work, stop the dispatcher, free the server. Returns the
+ * server's sticky error (UHNSW_OK if its launches all succeeded); the
+ * message of the last failure any serving call met is then what
+ * uhnsw_last_error(ctx) returns. */
 int uhnsw_serve_stop(uhnsw_server *srv);
 
 #ifdef __cplusplus

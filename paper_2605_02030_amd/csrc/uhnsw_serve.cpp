@@ -283,6 +283,13 @@ void dispatch_loop(uhnsw_server *S, std::unique_lock<std::mutex> &lk) {
     }
 }
 
+// A failure message from the caller's thread: kept with the server (the
+// dispatcher may be using the context) and handed to the context by stop.
+void note_error(uhnsw_server *S, const char *msg) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->err = msg;
+}
+
 }  // namespace
 
 extern "C" {
@@ -379,7 +386,9 @@ static int serve_start_body(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw
 
 int uhnsw_serve_start(uhnsw_ctx *ctx, const uhnsw_serve_config *cfg, uhnsw_server **out) {
     const auto body = [&] { return serve_start_body(ctx, cfg, out); };
-    return uhnsw::no_throw("uhnsw_serve_start", body, [&](const char *w) { if (ctx) uhnsw::ctx_set_error(ctx, w); });
+    return uhnsw::no_throw("uhnsw_serve_start", body, [&](const char *w) {
+        if (ctx) uhnsw::ctx_set_error(ctx, w);
+    });
 }
 
 static int serve_submit_body(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
@@ -406,7 +415,7 @@ static int serve_submit_body(uhnsw_server *S, const float *q, float p, int32_t k
 
 int uhnsw_serve_submit(uhnsw_server *S, const float *q, float p, int32_t k, int32_t ef, uint64_t tag) {
     const auto body = [&] { return serve_submit_body(S, q, p, k, ef, tag); };
-    return uhnsw::no_throw("uhnsw_serve_submit", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
+    return uhnsw::no_throw("uhnsw_serve_submit", body, [&](const char *w) { if (S) note_error(S, w); });
 }
 
 static int serve_poll_body(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int32_t *n_out) {
@@ -424,7 +433,7 @@ static int serve_poll_body(uhnsw_server *S, uhnsw_serve_result *out, int32_t max
 
 int uhnsw_serve_poll(uhnsw_server *S, uhnsw_serve_result *out, int32_t max, int32_t *n_out) {
     const auto body = [&] { return serve_poll_body(S, out, max, n_out); };
-    return uhnsw::no_throw("uhnsw_serve_poll", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
+    return uhnsw::no_throw("uhnsw_serve_poll", body, [&](const char *w) { if (S) note_error(S, w); });
 }
 
 int uhnsw_serve_info(uhnsw_server *S, int64_t *info) {
@@ -453,6 +462,12 @@ int uhnsw_serve_stop(uhnsw_server *S) {
     if (S->th.joinable()) S->th.join();
     const int rc = S->error.load();
     for (auto &L : S->lanes) free_lane(L);
+    if (!S->err.empty()) {  // the dispatcher has ended: the context is the caller's again
+        try {
+            uhnsw::ctx_set_error(S->ctx, S->err.c_str());
+        } catch (...) {
+        }
+    }
     uhnsw::ctx_servers(S->ctx, -1);
     delete S;
     return rc;
@@ -505,7 +520,7 @@ int uhnsw_serve_drive(uhnsw_server *S, int64_t n, const float *queries, const in
     const auto body = [&] {
         return serve_drive_body(S, n, queries, qidx, p, k, ef, arrival_us, out_k, ids, dists, stats, times, status);
     };
-    return uhnsw::no_throw("uhnsw_serve_drive", body, [&](const char *w) { if (S) uhnsw::ctx_set_error(S->ctx, w); });
+    return uhnsw::no_throw("uhnsw_serve_drive", body, [&](const char *w) { if (S) note_error(S, w); });
 }
 
 }  // extern "C"

@@ -475,14 +475,16 @@ class Server:
         h = _P()
         rc = uhnsw_serve_start(ctx.h, ctypes.byref(c), ctypes.byref(h))
         if rc != UHNSW_OK:
-            raise UhnswError(rc, "uhnsw_serve_start failed")
+            raise UhnswError(rc, "uhnsw_serve_start: " + uhnsw_last_error(ctx.h).decode())
         self.h, self.ctx, self.d, self.cfg = h, ctx, ctx.d, c
         if not hasattr(ctx, "_servers"):
             ctx._servers = weakref.WeakSet()
         ctx._servers.add(self)
 
     def submit(self, q, p, k, ef, tag) -> int:
-        q = np.ascontiguousarray(q, np.float32)
+        q = np.ascontiguousarray(q, np.float32).ravel()
+        if q.size != self.d:  # the library copies d floats
+            raise ValueError(f"query of {q.size} values, the index has d = {self.d}")
         return uhnsw_serve_submit(self.h, q.ctypes.data, float(p), int(k), int(ef), int(tag))
 
     def poll(self, max_n=256):
@@ -506,14 +508,20 @@ class Server:
         row. With qidx, arrival i carries queries[qidx[i]] (p, k, ef, arrival_us
         are per arrival)."""
         queries = np.ascontiguousarray(queries, np.float32)
+        if queries.ndim != 2 or queries.shape[1] != self.d:
+            raise ValueError(f"queries: (m, {self.d}) expected, got {queries.shape}")
         n = queries.shape[0] if qidx is None else len(qidx)
         if qidx is not None:
             qidx = np.ascontiguousarray(qidx, np.int32)
-            assert qidx.min() >= 0 and qidx.max() < queries.shape[0]
+            if n and (qidx.min() < 0 or qidx.max() >= queries.shape[0]):
+                raise ValueError("qidx: a row index outside queries")
         p = np.ascontiguousarray(p, np.float32)
         k = np.ascontiguousarray(k, np.int32)
         ef = np.ascontiguousarray(ef, np.int32)
         arr = np.ascontiguousarray(arrival_us, np.float64)
+        for name, a in (("p", p), ("k", k), ("ef", ef), ("arrival_us", arr)):
+            if a.ndim != 1 or a.shape[0] != n:  # the library reads one value per arrival
+                raise ValueError(f"{name}: {a.shape}, expected ({n},)")
         ok = int(out_k or self.cfg.k_max)
         ids = np.empty((n, ok), np.int64)
         dists = np.empty((n, ok), np.float32)
@@ -533,7 +541,7 @@ class Server:
             rc = uhnsw_serve_stop(self.h)
             self.h = None
             if rc != UHNSW_OK:
-                raise UhnswError(rc, "server ended with an error")
+                raise UhnswError(rc, "server ended with an error: " + uhnsw_last_error(self.ctx.h).decode())
 
     def __del__(self):
         try:

@@ -111,6 +111,13 @@ def test_admission_busy_and_budget(torch_cuda, ctxs, wl1):
             pass
         assert srv.submit(q[0], 0.3, k[0], ef[0], 1) == uhnsw.UHNSW_EINVAL
         assert srv.submit(q[0], p[0], 101, 128, 1) == uhnsw.UHNSW_EINVAL
+        # arrays the library would read past are refused by the binding
+        with pytest.raises(ValueError):
+            srv.submit(q[0][:-1], p[0], k[0], ef[0], 1)
+        with pytest.raises(ValueError):
+            srv.drive(q[:4], p[:3], k[:4], ef[:4], np.zeros(4))
+        with pytest.raises(ValueError):
+            srv.drive(q[:4], p[:4], k[:4], ef[:4], np.zeros(4), qidx=np.array([0, 1, 2, 4], np.int32))
     finally:
         srv.stop()
     with pytest.raises(uhnsw.UhnswError) as e:
