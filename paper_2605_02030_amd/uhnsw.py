@@ -314,10 +314,15 @@ class Context:
     def search(self, queries, p, k, ef, params: uhnsw_params | None = None, k_stride: int | None = None):
         """Host arrays in, host arrays out (synchronous)."""
         queries = np.ascontiguousarray(queries, np.float32)
+        if queries.ndim != 2 or (self.d and queries.shape[1] != self.d):
+            raise ValueError(f"queries: (nq, {self.d}) expected, got {queries.shape}")
         nq = queries.shape[0]
         p = np.ascontiguousarray(p, np.float32)
         k = np.ascontiguousarray(k, np.int32)
         ef = np.ascontiguousarray(ef, np.int32)
+        for name, a in (("p", p), ("k", k), ("ef", ef)):
+            if a.ndim != 1 or a.shape[0] != nq:  # the library reads one value per query
+                raise ValueError(f"{name}: {a.shape}, expected ({nq},)")
         ks = int(k_stride if k_stride is not None else (k.max() if nq else 1))
         ids = np.empty((nq, ks), np.int64)
         dists = np.empty((nq, ks), np.float32)
