@@ -214,12 +214,15 @@ def timed(form, steps, warmup, wl, rate_khz):
             form.step(timing=True, graph=False)
             split.append(form.ctx.last_timing_split())
     pre, walk, ver = (float(np.mean([x[i] for x in split])) for i in range(3))
+    walks = np.array([x[1] for x in split])
     st = form.stats_np()
     t0c = st["t_begin"].astype(np.int64)
     t1c = st["t_end"].astype(np.int64)
     start = t0c.min()
     lat_ms = ((t1c - start) % (1 << 32)) / rate_khz  # ticks -> ms
     return dict(total_s=total, prepass_ms=pre, walk_ms=walk, verify_ms=ver,
+                walk_reps=len(walks), walk_ms_median=float(np.median(walks)),
+                walk_ms_range=[float(walks.min()), float(walks.max())],
                 p50_ms=float(np.percentile(lat_ms, 50)), p99_ms=float(np.percentile(lat_ms, 99)), stats=st,
                 n_b=float(st["n_b"].mean()), n_exp=float(st["n_exp"].mean()), n_p=float(st["n_p"].mean()),
                 flags=int((st["flags"] != 0).sum()))
@@ -779,6 +782,8 @@ def main():
                            ms_per_step=round(r["total_s"] * 1e3 / a.steps, 4), p50_ms=round(r["p50_ms"], 4),
                            p99_ms=round(r["p99_ms"], 4), prepass_ms=round(r["prepass_ms"], 4),
                            walk_ms=round(r["walk_ms"], 4), verify_ms=round(r["verify_ms"], 4),
+                           walk_reps=r["walk_reps"], walk_ms_median=round(r["walk_ms_median"], 4),
+                           walk_ms_range=[round(x, 4) for x in r["walk_ms_range"]],
                            mean_n_b=round(r["n_b"], 1), mean_n_exp=round(r["n_exp"], 1),
                            mean_n_p=round(r["n_p"], 2), flagged=r["flags"], sweep=table)
         if persistent:
