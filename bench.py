@@ -209,8 +209,8 @@ def timed(form, steps, warmup, wl, rate_khz):
         split.append(form.ctx.last_timing_split())  # waits for this step's events
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
-    if form.pipeline > 1:  # one launch's own kernels, measured alone after the timed region
-        for _ in range(3):
+    if form.pipeline > 1:  # one launch's own kernels, measured alone after the timed region (5 launches)
+        for _ in range(5):
             form.step(timing=True, graph=False)
             split.append(form.ctx.last_timing_split())
     pre, walk, ver = (float(np.mean([x[i] for x in split])) for i in range(3))
