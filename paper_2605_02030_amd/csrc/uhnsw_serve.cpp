@@ -480,7 +480,7 @@ static int serve_drive_body(uhnsw_server *S, int64_t n, const float *queries, co
         (n > 0 && (!queries || !p || !k || !ef || !arrival_us || !ids || !dists || !times || !status)))
         return UHNSW_EINVAL;
     const auto t0 = std::chrono::steady_clock::now();
-    const double off = now_us(S->t0);  // server clock at the driver's time zero
+    const double off = now_us(S->t0);  // server clock at this call's time zero
     int64_t next = 0, got = 0;
     std::vector<uhnsw_serve_result> buf(256);
     while (got < n) {
